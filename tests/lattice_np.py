@@ -1,0 +1,65 @@
+"""Test-side lattice helpers, independent of the oracle's C code: shells of Z^5 by
+direct enumeration, coordinates (x0 fastest), and cluster labels of an occupied
+set by scipy's connected_components (a library graph routine)."""
+import itertools
+
+import numpy as np
+from scipy.sparse import coo_matrix
+from scipy.sparse.csgraph import connected_components
+
+
+def shell_offsets(mask):
+    out = []
+    for d in itertools.product(range(-2, 3), repeat=5):
+        r2 = sum(x * x for x in d)
+        if 1 <= r2 <= 7 and mask & (1 << (r2 - 1)):
+            out.append(d)
+    return np.array(out, dtype=np.int64).reshape(-1, 5)
+
+
+def coords(L, sites):
+    sites = np.asarray(sites, dtype=np.int64)
+    return np.stack([(sites // L**j) % L for j in range(5)], axis=-1)
+
+
+def components(L, mask, occupied_sites):
+    """Labels (smallest member index; -1 for empty) of the clusters formed by the
+    occupied sites under the zone-mask neighbourhood with free boundaries."""
+    N = L**5
+    occ = np.zeros(N, dtype=bool)
+    occ[np.asarray(occupied_sites, dtype=np.int64)] = True
+    idx = np.nonzero(occ)[0]
+    x = coords(L, idx)
+    rows, cols = [], []
+    for d in shell_offsets(mask):
+        y = x + d
+        inb = ((y >= 0) & (y < L)).all(axis=1)
+        t = (y[inb] * (L ** np.arange(5))).sum(axis=1)
+        ok = occ[t]
+        rows.append(idx[inb][ok])
+        cols.append(t[ok])
+    rows = np.concatenate(rows) if rows else np.zeros(0, np.int64)
+    cols = np.concatenate(cols) if cols else np.zeros(0, np.int64)
+    g = coo_matrix((np.ones(len(rows)), (rows, cols)), shape=(N, N))
+    _, lab = connected_components(g, directed=False)
+    out = np.full(N, -1, dtype=np.int64)
+    # canonical label: smallest site index in the component
+    comp_min = {}
+    for i in idx:
+        c = lab[i]
+        if c not in comp_min:
+            comp_min[c] = i
+    for i in idx:
+        out[i] = comp_min[lab[i]]
+    return out
+
+
+def spans(L, labels):
+    """True if some cluster has members at x0 = 0 and at x0 = L-1."""
+    occ = np.nonzero(labels >= 0)[0]
+    if len(occ) == 0:
+        return False
+    x0 = occ % L
+    lo = set(labels[occ[x0 == 0]].tolist())
+    hi = set(labels[occ[x0 == L - 1]].tolist())
+    return bool(lo & hi)

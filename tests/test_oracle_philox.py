@@ -1,0 +1,70 @@
+"""Pins of the oracle's Philox4x32-10 keys and its sort (not GPU).
+
+No published known-answer vectors are available here, so the pin is agreement
+between two implementations written separately from the SC'11 definition (the
+oracle's C and tests/philox_np.py), plus statistical uniformity of the keys and
+the order's defining invariants checked against NumPy's own lexsort.
+"""
+import numpy as np
+import pytest
+from scipy import stats
+
+import philox_np
+
+
+def test_philox_block_matches_independent_numpy(nzo):
+    rng = np.random.default_rng(1)
+    for _ in range(200):
+        ctr = rng.integers(0, 2**32, size=4, dtype=np.uint64)
+        key = rng.integers(0, 2**32, size=2, dtype=np.uint64)
+        got = nzo.philox4x32_10(ctr.astype(np.uint32), key.astype(np.uint32))
+        want = philox_np.philox4x32_10(ctr[0], ctr[1], ctr[2], ctr[3], key[0], key[1])
+        assert [int(x) for x in got] == [int(w) for w in want]
+
+
+@pytest.mark.parametrize("seed,sample", [(0, 0), (1, 2), (0xDEADBEEFCAFEF00D, 2**40 + 7)])
+def test_site_key_layout(nzo, seed, sample):
+    sites = np.arange(0, 5000, 37, dtype=np.uint64)
+    want = philox_np.site_keys(seed, sample, sites)
+    got = np.array([nzo.key(seed, sample, int(s)) for s in sites], dtype=np.uint64)
+    assert (got == want).all()
+    # the tag word is part of the counter
+    assert nzo.key(seed, sample, 5, 1) != nzo.key(seed, sample, 5, 0)
+
+
+def test_keys_uniform_chi2():
+    k = philox_np.site_keys(1234, 0, np.arange(1 << 18, dtype=np.uint64))
+    for shift in (60, 32, 0):
+        b = ((k >> np.uint64(shift)) & np.uint64(15)).astype(np.int64)
+        cnt = np.bincount(b, minlength=16)
+        p = stats.chisquare(cnt).pvalue
+        assert p > 1e-4, (shift, p)
+
+
+def test_keys_distinct_across_samples_and_seeds():
+    s = np.arange(4096, dtype=np.uint64)
+    a = philox_np.site_keys(1, 0, s)
+    b = philox_np.site_keys(1, 1, s)
+    c = philox_np.site_keys(2, 0, s)
+    assert len(set(a.tolist()) | set(b.tolist()) | set(c.tolist())) == 3 * 4096
+
+
+@pytest.mark.parametrize("L,seed,sample", [(3, 5, 0), (4, 77, 9), (5, 1, 123)])
+def test_order_is_lexsort_of_keys(nzo, L, seed, sample):
+    N = L**5
+    k = philox_np.site_keys(seed, sample, np.arange(N, dtype=np.uint64))
+    want = np.lexsort((np.arange(N), k)).astype(np.uint32)
+    got = nzo.order(L, seed, sample)
+    assert (got == want).all()
+    assert sorted(got.tolist()) == list(range(N))
+    assert (np.diff(k[got].astype(np.float64)) >= 0).all() or (k[got][1:] >= k[got][:-1]).all()
+
+
+def test_sort_ties_break_by_index(nzo):
+    keys = np.array([7, 3, 7, 3, 0, 7, 2**64 - 1, 0], dtype=np.uint64)
+    got = nzo.sort_keyed(keys)
+    assert got.tolist() == [4, 7, 1, 3, 0, 2, 5, 6]
+    rng = np.random.default_rng(5)
+    keys = rng.integers(0, 4, size=1000).astype(np.uint64)
+    got = nzo.sort_keyed(keys)
+    assert (got == np.lexsort((np.arange(1000), keys))).all()
