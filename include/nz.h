@@ -1,0 +1,200 @@
+/*
+ * nz.h -- C ABI of libnz: the Newman-Ziff first-spanning sweep for random site
+ * percolation on the five-dimensional simple hypercubic lattice sc(5) with
+ * complex neighbourhoods, on one AMD Instinct MI355X (gfx950).
+ *
+ * The method (Malarz & Woloszyn, "Random site percolation with complex
+ * neighborhoods in five dimension"):
+ *   - Sec. I: sites of an L^5 lattice are occupied at random; a cluster that
+ *     connects opposite borders "spans"; here the borders are the faces
+ *     x0 = 0 and x0 = L-1 and boundaries are free (no wrapping);
+ *   - Sec. II.A.2, eqs. (7)-(8), Table I: a neighbourhood is any non-empty set
+ *     of coordination zones 1..7, zone k being the shell r^2 = k (10, 40, 80,
+ *     90, 112, 240, 320 sites); bit k-1 of zone_mask selects zone k;
+ *   - Sec. II.B: the Newman-Ziff construction adds occupied sites one at a time
+ *     in a random order and merges clusters with union-find; a binomial
+ *     convolution turns per-n results into functions of p.
+ *
+ * Conventions shared by every entry point:
+ *   - site i has coordinates x_j = floor(i / L^j) mod L (x0 fastest);
+ *   - the occupation order of sample s under seed is the sites sorted by
+ *     (K(i), i), K(i) = (w1 << 32) | w0 where (w0..w3) = Philox4x32-10 of
+ *     counter (i, lo32(s), hi32(s), 0) under key (lo32(seed), hi32(seed));
+ *   - n* (1-based) is the number of occupied sites when a spanning cluster first
+ *     exists, mass its size at that moment; n* = mass = 0 when even the full
+ *     lattice does not span (only L = 2 with zones 6 and/or 7 alone).
+ *
+ * Every function returns an int status (NZ_OK or a negative NZ_E* code); on
+ * failure nz_last_error() describes the cause and output buffers are left
+ * unspecified.  No exception crosses the ABI.  Functions are thread-compatible:
+ * calls from different host threads must not share a workspace.
+ */
+#ifndef NZ_H
+#define NZ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define NZ_OK 0
+#define NZ_EINVAL (-1)        /* an argument is out of range or a pointer is NULL */
+#define NZ_EUNSUPPORTED (-2)  /* valid request this library does not implement */
+#define NZ_ENOMEM (-3)        /* a host or device allocation failed */
+#define NZ_EDEVICE (-4)       /* a HIP runtime call or kernel launch failed */
+#define NZ_EWORKSPACE (-5)    /* the caller's workspace is too small */
+
+#define NZ_FREE 0             /* free boundaries: the only boundary implemented */
+
+/* Message describing the last failure on the calling thread (never NULL). */
+const char *nz_last_error(void);
+
+/* ABI version of this header. */
+#define NZ_ABI_VERSION 1
+int nz_abi_version(void);
+
+/* Number of sites z = |D(zone_mask)| of a neighbourhood (eq. (7)); -1 when
+ * zone_mask is outside [1, 127]. */
+int nz_coordination(uint32_t zone_mask);
+
+/*
+ * nz_sweep -- n* and spanning mass of samples 0 .. nsamples-1 (Sec. II.B).
+ *   L          lattice side, 1 <= L <= 55 (N = L^5 < 2^29);
+ *   zone_mask  1..127;  boundary  NZ_FREE;  seed  any 64-bit value;
+ *   nstar      HOST array of nsamples int32, written;
+ *   mass       HOST array of nsamples int32, written; may be NULL.
+ * Synchronous; allocates and frees its own device memory; runs on the current
+ * HIP device and its default stream.  Plain sweep (no prefill).
+ */
+int nz_sweep(int32_t L, uint32_t zone_mask, int32_t boundary, int64_t nsamples, uint64_t seed,
+             int32_t *nstar, int32_t *mass);
+
+/*
+ * nz_canonical -- R_L(p) = sum_n C(N,n) p^n (1-p)^(N-n) F_n (Sec. II.B, the
+ * binomial convolution), F_n = sum_{1<=m<=n} hist[m] / sum_{m>=0} hist[m].
+ *   hist    HOST, hist_len = N + 1 counts; hist[0] = samples that never span;
+ *   p_grid  HOST, np values in [0, 1];  R  HOST, np doubles, written.
+ * FP64 on the host; binomial weights built outward from the mode by their
+ * ratio recurrence, so no factorial or log-gamma is formed.
+ */
+int nz_canonical(const uint64_t *hist, int64_t hist_len, const double *p_grid, int64_t np,
+                 double *R);
+
+/*
+ * Batched device API.  One nz_job describes nsamples consecutive samples
+ * (Philox sample indices sample0 ..) of one (L, zone_mask) lattice.
+ *   n0        -1: plain sweep from the empty lattice.
+ *             >= 0: learned prefill (Sec. II.B construction started from a
+ *             bulk state): every site whose key lies below
+ *             floor(n0 / N * 2^64) is occupied at once and its clusters are
+ *             labelled by parallel connected components; the sequential sweep
+ *             continues from there.  If that bulk state already spans, the
+ *             sample backs off to n0 - backoff (then to 0) and is redone, so n*
+ *             and mass never depend on n0.
+ *   backoff   sites to back off by on the first span at n0 (0: straight to 0).
+ *   band_hi   expected upper bound on n* used to size the key band (sites;
+ *             0: library default).  Never changes results, only work.
+ *   prio      relative expected cost of a sample, for longest-first
+ *             scheduling (0: library estimate).  Never changes results.
+ */
+typedef struct {
+    int32_t L;
+    uint32_t zone_mask;
+    int32_t boundary;
+    int32_t reserved;
+    uint64_t seed;
+    int64_t sample0;
+    int64_t nsamples;
+    int64_t n0;
+    int64_t backoff;
+    int64_t band_hi;
+    double prio;
+} nz_job;
+
+/*
+ * Tuning knobs (all 0 = automatic).  None of them changes any output.
+ *   residency       1: occupancy bitset in LDS (L^5 / 8 bytes must fit);
+ *                   2: everything in HBM; 3: bitset and parents in LDS.
+ *   wg_waves        waves per workgroup of the sweep (1..16).
+ *   waves_per_simd  resident sweep waves per SIMD of the persistent launch.
+ *   bucket_log2     log2 of the mean number of keys per sort bucket (4..10).
+ */
+typedef struct {
+    int32_t residency;
+    int32_t wg_waves;
+    int32_t waves_per_simd;
+    int32_t bucket_log2;
+} nz_tuning;
+
+/* Device workspace bytes that lets nz_sweep_batch run the jobs with all their
+ * samples resident at once.  Smaller workspaces (down to the size needed by one
+ * sample of the largest L) are accepted and processed in chunks. */
+int nz_batch_workspace_bytes(const nz_job *jobs, int32_t njobs, const nz_tuning *tune,
+                             size_t *bytes);
+
+/*
+ * nz_sweep_batch -- all samples of all jobs, scheduled longest-first over one
+ * persistent sweep launch per chunk of the workspace.
+ *   jobs, njobs    HOST array;
+ *   d_ws, ws_bytes DEVICE workspace owned by the caller (256-byte aligned);
+ *   d_nstar        DEVICE int32 array, sum of nsamples entries, written in job
+ *                  order (job 0's samples first);
+ *   d_mass         DEVICE int32 array like d_nstar; may be NULL;
+ *   h_backoffs     HOST int32 array of njobs, backoff count per job; may be NULL;
+ *   tune           may be NULL;  stream  hipStream_t (NULL: default stream).
+ * Returns after the results are in d_nstar / d_mass (the call synchronises the
+ * stream, because samples whose key band or bucket ran short are redone).
+ */
+int nz_sweep_batch(const nz_job *jobs, int32_t njobs, void *d_ws, size_t ws_bytes,
+                   int32_t *d_nstar, int32_t *d_mass, int32_t *h_backoffs,
+                   const nz_tuning *tune, void *stream);
+
+/* Statistics of the last nz_sweep_batch on the calling thread: chunks, samples
+ * redone because their band ran out, because a bucket overflowed, and backoffs.
+ * stats[0..3]; returns NZ_OK. */
+int nz_last_batch_stats(int64_t stats[4]);
+
+/* Phase timing of nz_sweep_batch with HIP events recorded on the caller's
+ * stream around each group of launches.  nz_set_timing(1) turns it on for later
+ * calls on the calling thread (0 turns it off).  nz_last_batch_timing fills
+ * ms[0..5]: milliseconds in keys (with clearing), bulk connected components,
+ * bucket sort, sweep, the whole call, and ms[5] = number of sweep launches. */
+int nz_set_timing(int enable);
+int nz_last_batch_timing(double ms[6]);
+
+/*
+ * MLP that predicts the mean and spread of n* / N for the learned prefill: three dense
+ * layers 8 -> 64 -> 64 -> 2 with tanh after the first two.  Inputs per row are
+ * the seven zone-mask bits and a standardised ln L; outputs (u, v) estimate
+ * (ln mean, ln std) of n* / N.  Weights are BF16, arithmetic FP32.
+ *
+ * Parameter layout (NZ_MLP_NPARAM values, row-major, "in x out"):
+ *   W1[8][64] b1[64] W2[64][64] b2[64] W3[64][2] b3[2].
+ * All pointers are DEVICE pointers; B >= 1 rows; stream may be NULL.
+ *   params_bf16   NZ_MLP_NPARAM uint16 (bfloat16 bit patterns);
+ *   x             float [B][8];  y  float [B][2];
+ *   act           float [B][NZ_MLP_NACT] cache of hidden activations written by
+ *                 forward and read by backward;
+ *   dy            float [B][2] gradient of the loss w.r.t. y;
+ *   grad          float [NZ_MLP_NPARAM], written (not accumulated);
+ *   params_fp32   FP32 master weights, updated in place by nz_mlp_adam, which
+ *                 also rewrites params_bf16 (round-to-nearest-even);
+ *   adam_m, adam_v  float [NZ_MLP_NPARAM] moment buffers, updated in place;
+ *   hyper         HOST float[5] = {lr, beta1, beta2, eps, weight_decay};
+ *   step          1-based Adam step (bias correction).
+ */
+#define NZ_MLP_NPARAM (8 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2)
+#define NZ_MLP_NACT 128
+int nz_mlp_forward(const uint16_t *params_bf16, const float *x, float *y, float *act, int32_t B,
+                   void *stream);
+int nz_mlp_backward(const uint16_t *params_bf16, const float *x, const float *act,
+                    const float *dy, float *grad, int32_t B, void *stream);
+int nz_mlp_adam(float *params_fp32, uint16_t *params_bf16, const float *grad, float *adam_m,
+                float *adam_v, const float hyper[5], int32_t step, void *stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif

@@ -1,0 +1,814 @@
+// nz_api.cpp -- the C ABI of libnz (include/nz.h): argument checking, the
+// neighbourhood tables, the per-sample plan (key band, buckets, prefill),
+// workspace layout, chunked launches on one stream and the redo loop for the
+// rare samples whose band or bucket ran short or whose prefill already spans.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdlib>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <string>
+#include <vector>
+
+#include "../../include/nz.h"
+#include "nz_internal.h"
+#include "nz_launch.h"
+
+#define NZ_API extern "C" __attribute__((visibility("default")))
+
+namespace {
+
+thread_local std::string g_err = "no error";
+thread_local int64_t g_stats[4] = {0, 0, 0, 0};
+thread_local bool g_timing = false;
+thread_local double g_ms[6] = {0, 0, 0, 0, 0, 0};
+
+// Events bracketing the phases of one chunk (keys, prefill, sort, sweep).
+struct PhaseEvents {
+    hipEvent_t ev[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    bool ok = false;
+    PhaseEvents()
+    {
+        ok = true;
+        for (auto &e : ev) ok = ok && hipEventCreate(&e) == hipSuccess;
+    }
+    ~PhaseEvents()
+    {
+        for (auto &e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
+};
+
+int fail(int code, const char *fmt, ...)
+{
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    g_err = buf;
+    return code;
+}
+
+#define HIP_TRY(call)                                                                        \
+    do {                                                                                     \
+        hipError_t e_ = (call);                                                              \
+        if (e_ != hipSuccess)                                                                \
+            return fail(NZ_EDEVICE, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_),   \
+                        __FILE__, __LINE__);                                                 \
+    } while (0)
+
+int64_t pow5(int64_t L) { return L * L * L * L * L; }
+
+// ---------------------------------------------------------------------------
+// Neighbourhoods (Sec. II.A.2, Table I): zone k is the shell |d|^2 = k of Z^5,
+// k = 1..7.  Every shell vector has |d_j| <= 2.  The table lists first the
+// vectors whose last non-zero coordinate is negative and then their negations
+// in the same order, so its first half holds one vector of every +-d pair.
+
+std::vector<std::array<int, 5>> zone_vectors(uint32_t mask)
+{
+    std::vector<std::array<int, 5>> neg;
+    for (int k = 1; k <= 7; ++k) {
+        if (!(mask >> (k - 1) & 1u)) continue;
+        for (int v = 0; v < 3125; ++v) {
+            std::array<int, 5> d;
+            int r2 = 0, rem = v;
+            for (int j = 0; j < 5; ++j) {
+                d[j] = rem % 5 - 2;
+                rem /= 5;
+                r2 += d[j] * d[j];
+            }
+            if (r2 != k) continue;
+            int last = 0;
+            for (int j = 4; j >= 0; --j)
+                if (d[j] != 0) {
+                    last = d[j];
+                    break;
+                }
+            if (last < 0) neg.push_back(d);
+        }
+    }
+    std::vector<std::array<int, 5>> all = neg;
+    for (const auto &d : neg) all.push_back({-d[0], -d[1], -d[2], -d[3], -d[4]});
+    return all;
+}
+
+std::vector<NzOffset> build_table(uint32_t mask, int32_t L)
+{
+    std::vector<NzOffset> t;
+    for (const auto &d : zone_vectors(mask)) {
+        NzOffset o;
+        int64_t stride = 0, p = 1;
+        uint32_t code = 0;
+        for (int j = 0; j < 5; ++j) {
+            stride += d[j] * p;
+            p *= L;
+            code |= 1u << (5 * j + d[j] + 2);
+        }
+        o.stride = static_cast<int32_t>(stride);
+        o.code = code;
+        t.push_back(o);
+    }
+    return t;
+}
+
+// ---------------------------------------------------------------------------
+// Device facts.
+
+struct Device {
+    int id = -1;
+    int cus = 256;
+    size_t lds_per_block = 65536;
+    size_t lds_per_cu = 65536;
+};
+
+int device_info(Device &dev)
+{
+    int id = 0;
+    HIP_TRY(hipGetDevice(&id));
+    static thread_local std::map<int, Device> cache;
+    auto it = cache.find(id);
+    if (it != cache.end()) {
+        dev = it->second;
+        return NZ_OK;
+    }
+    hipDeviceProp_t p;
+    HIP_TRY(hipGetDeviceProperties(&p, id));
+    dev.id = id;
+    dev.cus = p.multiProcessorCount;
+    dev.lds_per_block = p.sharedMemPerBlock;
+    dev.lds_per_cu = p.maxSharedMemoryPerMultiProcessor ? p.maxSharedMemoryPerMultiProcessor : p.sharedMemPerBlock;
+    int optin = 0;
+    if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, id) == hipSuccess && optin > 0)
+        dev.lds_per_block = std::max(dev.lds_per_block, static_cast<size_t>(optin));
+    cache[id] = dev;
+    return NZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Per-sample plan.
+
+constexpr int kMaxChunk = 16384;
+constexpr size_t kAlign = 256;
+
+size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
+
+// Threshold coefficient of p_c = c / (z + b) fitted over Table I (Sec. III.B:
+// c ~ 1.553, b ~ 1.01); used only to size key bands and to order work.
+double pc_prior(int z) { return 1.553 / (z + 1.01); }
+
+struct Plan {
+    int32_t job;
+    int64_t sample;      // Philox sample index
+    int32_t out;         // index into the caller's output arrays
+    int32_t L;
+    uint32_t mask;
+    int64_t n0;          // current prefill rank (0: plain)
+    int64_t backoff;     // backoff step still available (0: next backoff goes to 0)
+    int64_t band_hi;     // upper end of the key band in sites
+    int32_t shift_adj;   // extra halvings of the bucket width
+    int32_t prefix_mul;  // prefill list capacity multiplier
+    double prio;
+};
+
+uint64_t rank_to_key(int64_t n, int64_t N)
+{
+    // floor(n / N * 2^64) for 0 <= n < N
+    unsigned __int128 v = (static_cast<unsigned __int128>(static_cast<uint64_t>(n)) << 64) / static_cast<uint64_t>(N);
+    return static_cast<uint64_t>(v);
+}
+
+struct Sizes {
+    uint64_t T0;
+    int32_t nb, cap, shift, full, prefix_cap;
+    size_t par, occ, keys, sites, counts, prefix, total;
+};
+
+Sizes plan_sizes(const Plan &p, int bucket_log2)
+{
+    Sizes s{};
+    const int64_t N = pow5(p.L);
+    s.T0 = p.n0 > 0 ? rank_to_key(p.n0, N) : 0;
+    int lgN = 0;
+    while ((int64_t(1) << lgN) < N) ++lgN;
+    int shift = 64 + bucket_log2 - lgN - p.shift_adj;
+    shift = std::max(1, std::min(63, shift));
+    s.shift = shift;
+    const unsigned __int128 span_full = (static_cast<unsigned __int128>(1) << 64) - s.T0;
+    unsigned __int128 span;
+    if (p.band_hi >= N) {
+        span = span_full;
+        s.full = 1;
+    } else {
+        const uint64_t Thi = rank_to_key(std::max<int64_t>(p.band_hi, p.n0 + 1), N);
+        span = Thi > s.T0 ? Thi - s.T0 : 1;
+        s.full = 0;
+    }
+    const unsigned __int128 w = static_cast<unsigned __int128>(1) << shift;
+    const unsigned __int128 nb = (span + w - 1) / w;
+    s.nb = static_cast<int32_t>(std::max<unsigned __int128>(1, nb));
+    const double mean = std::ldexp(static_cast<double>(N), shift - 64);
+    int cap = static_cast<int>(std::ceil(mean + 8.0 * std::sqrt(mean) + 16.0));
+    cap = (cap + 15) / 16 * 16;
+    s.cap = std::max(16, std::min(cap, 4096));
+    if (p.n0 > 0) {
+        const double e = static_cast<double>(p.n0);
+        s.prefix_cap = static_cast<int32_t>(std::min<double>(static_cast<double>(N), (e + 8.0 * std::sqrt(e) + 64.0) * p.prefix_mul));
+    } else {
+        s.prefix_cap = 0;
+    }
+    s.par = align_up(static_cast<size_t>(N) * 4);
+    s.occ = align_up(static_cast<size_t>((N + 63) / 64) * 8);
+    s.keys = align_up(static_cast<size_t>(s.nb) * s.cap * 8);
+    s.sites = align_up(static_cast<size_t>(s.nb) * s.cap * 4);
+    s.counts = align_up(static_cast<size_t>(s.nb) * 4);
+    s.prefix = align_up(static_cast<size_t>(s.prefix_cap) * 4);
+    s.total = s.par + s.occ + s.keys + s.sites + s.counts + s.prefix;
+    return s;
+}
+
+int64_t default_band_hi(int32_t L, uint32_t mask, int64_t n0)
+{
+    const int64_t N = pow5(L);
+    if (N <= 8192) return N;
+    const int z = static_cast<int>(zone_vectors(mask).size());
+    const double frac = pc_prior(z) * (1.0 + 4.0 / std::sqrt(static_cast<double>(L)));
+    int64_t hi = static_cast<int64_t>(frac * N) + 4096;
+    hi = std::max(hi, n0 + 4096);
+    return std::min(hi, N);
+}
+
+size_t header_bytes(size_t table_entries, int32_t chunk)
+{
+    return align_up(table_entries * sizeof(NzOffset)) + align_up(chunk * sizeof(NzSample)) +
+           align_up(chunk * sizeof(NzState)) + 3 * align_up(chunk * sizeof(int32_t)) + kAlign;
+}
+
+struct Tune {
+    int residency = 0;
+    int wg_waves = 0;
+    int waves_per_simd = 0;
+    int bucket_log2 = 8;
+    int dcap = 64;
+};
+
+int check_job(const nz_job &j, int idx)
+{
+    if (j.L < 1 || j.L > 55) return fail(j.L < 1 ? NZ_EINVAL : NZ_EUNSUPPORTED, "job %d: L = %d outside [1, 55]", idx, j.L);
+    if (j.zone_mask < 1 || j.zone_mask > 127) return fail(NZ_EINVAL, "job %d: zone_mask %u outside [1, 127]", idx, j.zone_mask);
+    if (j.boundary != NZ_FREE) return fail(NZ_EUNSUPPORTED, "job %d: only free boundaries (NZ_FREE) are implemented", idx);
+    if (j.nsamples < 0) return fail(NZ_EINVAL, "job %d: nsamples < 0", idx);
+    if (j.sample0 < 0) return fail(NZ_EINVAL, "job %d: sample0 < 0", idx);
+    const int64_t N = pow5(j.L);
+    if (j.n0 < -1 || j.n0 >= N) return fail(NZ_EINVAL, "job %d: n0 = %lld outside [-1, N-1]", idx, (long long)j.n0);
+    if (j.backoff < 0) return fail(NZ_EINVAL, "job %d: backoff < 0", idx);
+    if (j.band_hi < 0) return fail(NZ_EINVAL, "job %d: band_hi < 0", idx);
+    return NZ_OK;
+}
+
+int read_tune(const nz_tuning *t, Tune &out)
+{
+    out = Tune{};
+    if (!t) return NZ_OK;
+    if (t->residency < 0 || t->residency > 3) return fail(NZ_EINVAL, "tuning: residency %d outside [0, 3]", t->residency);
+    if (t->wg_waves < 0 || t->wg_waves > 16) return fail(NZ_EINVAL, "tuning: wg_waves %d outside [0, 16]", t->wg_waves);
+    if (t->waves_per_simd < 0 || t->waves_per_simd > 8)
+        return fail(NZ_EINVAL, "tuning: waves_per_simd %d outside [0, 8]", t->waves_per_simd);
+    if (t->bucket_log2 != 0 && (t->bucket_log2 < 4 || t->bucket_log2 > 10))
+        return fail(NZ_EINVAL, "tuning: bucket_log2 %d outside [4, 10]", t->bucket_log2);
+    out.residency = t->residency;
+    out.wg_waves = t->wg_waves;
+    out.waves_per_simd = t->waves_per_simd;
+    if (t->bucket_log2) out.bucket_log2 = t->bucket_log2;
+    return NZ_OK;
+}
+
+int nch_for(int z)
+{
+    if (z <= 64) return 1;
+    if (z <= 128) return 2;
+    if (z <= 256) return 4;
+    if (z <= 512) return 8;
+    return 14;
+}
+
+// Debug override of the distinct-root list size (tests force early merges).
+int env_dcap()
+{
+    const char *e = getenv("NZ_DEBUG_DCAP");
+    if (!e) return 64;
+    int v = atoi(e);
+    return std::max(2, std::min(64, v));
+}
+
+// ---------------------------------------------------------------------------
+// The batch engine.
+
+struct TablePool {
+    std::map<std::pair<uint32_t, int32_t>, int32_t> index;
+    std::vector<NzOffset> entries;
+    int32_t get(uint32_t mask, int32_t L, int32_t *z)
+    {
+        auto key = std::make_pair(mask, L);
+        auto it = index.find(key);
+        if (it != index.end()) {
+            *z = static_cast<int32_t>(zone_vectors(mask).size());
+            return it->second;
+        }
+        auto t = build_table(mask, L);
+        const int32_t at = static_cast<int32_t>(entries.size());
+        entries.insert(entries.end(), t.begin(), t.end());
+        index[key] = at;
+        *z = static_cast<int32_t>(t.size());
+        return at;
+    }
+};
+
+int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_t *d_nstar, int32_t *d_mass,
+              int32_t *h_backoffs, const Tune &tune, hipStream_t st)
+{
+    Device dev;
+    if (int rc = device_info(dev)) return rc;
+    for (int k = 0; k < 4; ++k) g_stats[k] = 0;
+    for (int k = 0; k < 6; ++k) g_ms[k] = 0.0;
+    if (h_backoffs)
+        for (int j = 0; j < njobs; ++j) h_backoffs[j] = 0;
+
+    // tables for every (mask, L) of the batch live at the start of the workspace
+    TablePool pool;
+    std::vector<Plan> todo;
+    int64_t out = 0;
+    for (int j = 0; j < njobs; ++j) {
+        const nz_job &J = jobs[j];
+        int32_t z = 0;
+        pool.get(J.zone_mask, J.L, &z);
+        const int64_t N = pow5(J.L);
+        for (int64_t k = 0; k < J.nsamples; ++k) {
+            Plan p{};
+            p.job = j;
+            p.sample = J.sample0 + k;
+            p.out = static_cast<int32_t>(out++);
+            p.L = J.L;
+            p.mask = J.zone_mask;
+            p.n0 = J.n0 > 0 ? J.n0 : 0;
+            p.backoff = J.backoff;
+            p.band_hi = J.band_hi > 0 ? std::min<int64_t>(J.band_hi, N) : default_band_hi(J.L, J.zone_mask, p.n0);
+            if (p.band_hi <= p.n0) p.band_hi = std::min<int64_t>(N, p.n0 + 4096);
+            p.shift_adj = 0;
+            p.prefix_mul = 1;
+            p.prio = J.prio > 0 ? J.prio : static_cast<double>(std::max<int64_t>(1, p.band_hi - p.n0)) * (1.0 + z / 64.0);
+            todo.push_back(p);
+        }
+    }
+    if (out > 0x7FFFFFFF) return fail(NZ_EINVAL, "too many samples in one batch");
+    const size_t tab_bytes = align_up(pool.entries.size() * sizeof(NzOffset));
+
+    int rounds = 0;
+    while (!todo.empty()) {
+        if (++rounds > 64) return fail(NZ_EDEVICE, "samples still unfinished after 64 redo rounds");
+        std::stable_sort(todo.begin(), todo.end(), [](const Plan &a, const Plan &b) { return a.prio > b.prio; });
+        std::vector<Plan> redo;
+        size_t pos = 0;
+        while (pos < todo.size()) {
+            // ---- form a chunk: longest first, as many as the workspace holds
+            const int32_t cmax = static_cast<int32_t>(std::min<size_t>(kMaxChunk, todo.size() - pos));
+            const size_t head = header_bytes(pool.entries.size(), cmax);
+            if (head >= ws_bytes) return fail(NZ_EWORKSPACE, "workspace of %zu bytes is smaller than the %zu-byte header", ws_bytes, head);
+            std::vector<Plan> chunk;
+            std::vector<Sizes> sizes;
+            size_t used = head;
+            while (pos < todo.size() && static_cast<int32_t>(chunk.size()) < cmax) {
+                Sizes s = plan_sizes(todo[pos], tune.bucket_log2);
+                if (used + s.total > ws_bytes) break;
+                used += s.total;
+                chunk.push_back(todo[pos]);
+                sizes.push_back(s);
+                ++pos;
+            }
+            if (chunk.empty()) {
+                Sizes s = plan_sizes(todo[pos], tune.bucket_log2);
+                return fail(NZ_EWORKSPACE, "workspace of %zu bytes cannot hold one sample (needs %zu)", ws_bytes, head + s.total);
+            }
+            ++g_stats[0];
+            const int32_t n = static_cast<int32_t>(chunk.size());
+
+            // ---- descriptors, grouped by L for the keys launches
+            std::vector<int32_t> byL(n);
+            for (int32_t i = 0; i < n; ++i) byL[i] = i;
+            std::stable_sort(byL.begin(), byL.end(), [&](int32_t a, int32_t b) { return chunk[a].L < chunk[b].L; });
+            std::vector<NzSample> desc(n);
+            std::vector<int32_t> out_index(n), queue(n), prefill_list;
+            std::vector<int32_t> chunk_of_desc(n);
+            size_t off = head;
+            int32_t max_nb = 0, max_cap = 0, max_z = 0;
+            uint32_t max_N = 0;
+            int64_t max_hook = 0, max_site = 0;
+            std::vector<int32_t> desc_of_chunk(n);
+            for (int32_t di = 0; di < n; ++di) {
+                const int32_t ci = byL[di];
+                const Plan &p = chunk[ci];
+                const Sizes &s = sizes[ci];
+                const nz_job &J = jobs[p.job];
+                NzSample &d = desc[di];
+                std::memset(&d, 0, sizeof d);
+                d.seed = J.seed;
+                d.sample = static_cast<uint64_t>(p.sample);
+                d.T0 = s.T0;
+                d.L = p.L;
+                d.N = static_cast<int32_t>(pow5(p.L));
+                d.nb = s.nb;
+                d.cap = s.cap;
+                d.shift = s.shift;
+                d.full = s.full;
+                d.prefix_cap = s.prefix_cap;
+                d.tab = pool.get(p.mask, p.L, &d.z);
+                d.magic = p.L == 1 ? 0 : static_cast<uint64_t>(~0ull / static_cast<uint64_t>(p.L) + 1ull);
+                d.off_par = off; off += s.par;
+                d.off_occ = off; off += s.occ;
+                d.off_keys = off; off += s.keys;
+                d.off_sites = off; off += s.sites;
+                d.off_counts = off; off += s.counts;
+                d.off_prefix = off; off += s.prefix;
+                out_index[di] = p.out;
+                chunk_of_desc[di] = ci;
+                desc_of_chunk[ci] = di;
+                max_nb = std::max(max_nb, d.nb);
+                max_cap = std::max(max_cap, d.cap);
+                max_z = std::max(max_z, d.z);
+                max_N = std::max(max_N, static_cast<uint32_t>(d.N));
+                if (d.T0 != 0) {
+                    prefill_list.push_back(di);
+                    max_hook = std::max<int64_t>(max_hook, static_cast<int64_t>(s.prefix_cap) * (d.z / 2));
+                    max_site = std::max<int64_t>(max_site, s.prefix_cap);
+                }
+            }
+            for (int32_t q = 0; q < n; ++q) queue[q] = desc_of_chunk[q];   // chunk is in priority order
+
+            // ---- header layout
+            uint8_t *h = ws;
+            NzOffset *d_tabs = reinterpret_cast<NzOffset *>(h);
+            h += tab_bytes;
+            NzSample *d_desc = reinterpret_cast<NzSample *>(h);
+            h += align_up(cmax * sizeof(NzSample));
+            NzState *d_state = reinterpret_cast<NzState *>(h);
+            h += align_up(cmax * sizeof(NzState));
+            int32_t *d_queue = reinterpret_cast<int32_t *>(h);
+            h += align_up(cmax * sizeof(int32_t));
+            int32_t *d_outidx = reinterpret_cast<int32_t *>(h);
+            h += align_up(cmax * sizeof(int32_t));
+            int32_t *d_list = reinterpret_cast<int32_t *>(h);
+            h += align_up(cmax * sizeof(int32_t));
+            int32_t *d_qhead = reinterpret_cast<int32_t *>(h);
+
+            HIP_TRY(hipMemcpyAsync(d_tabs, pool.entries.data(), pool.entries.size() * sizeof(NzOffset), hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(d_desc, desc.data(), n * sizeof(NzSample), hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(d_queue, queue.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            HIP_TRY(hipMemcpyAsync(d_outidx, out_index.data(), n * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            if (!prefill_list.empty())
+                HIP_TRY(hipMemcpyAsync(d_list, prefill_list.data(), prefill_list.size() * sizeof(int32_t), hipMemcpyHostToDevice, st));
+            const int32_t zero = 0;
+            HIP_TRY(hipMemcpyAsync(d_qhead, &zero, sizeof zero, hipMemcpyHostToDevice, st));
+
+            // ---- launches
+            PhaseEvents *pe = nullptr;
+            static thread_local PhaseEvents *events = nullptr;
+            if (g_timing) {
+                if (!events) events = new PhaseEvents();
+                if (events->ok) pe = events;
+            }
+            if (pe) HIP_TRY(hipEventRecord(pe->ev[0], st));
+            HIP_TRY(nz::launch_clear(d_desc, n, ws, d_state, st));
+            for (int32_t a = 0; a < n;) {
+                int32_t b = a;
+                while (b < n && desc[b].N == desc[a].N) ++b;
+                HIP_TRY(nz::launch_keys(d_desc, a, b - a, desc[a].N, ws, d_state, st));
+                a = b;
+            }
+            if (pe) HIP_TRY(hipEventRecord(pe->ev[1], st));
+            if (!prefill_list.empty()) {
+                const int32_t bx_hook = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(2048, (max_hook + 1023) / 1024)));
+                const int32_t bx_site = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(1024, (max_site + 1023) / 1024)));
+                HIP_TRY(nz::launch_prefill(d_desc, d_list, static_cast<int32_t>(prefill_list.size()), bx_hook, bx_site, d_tabs, ws,
+                                           d_state, st));
+            }
+            if (pe) HIP_TRY(hipEventRecord(pe->ev[2], st));
+            HIP_TRY(nz::launch_sort(d_desc, n, max_nb, max_cap, ws, st));
+            if (pe) HIP_TRY(hipEventRecord(pe->ev[3], st));
+
+            int residency = tune.residency == 3 ? 2 : (tune.residency == 1 ? 1 : 0);
+            const uint32_t occ_words = ((max_N + 63) / 64) * 2;
+            uint32_t lds_words = residency == 2 ? occ_words + max_N : (residency == 1 ? occ_words : 0);
+            int wg_waves = tune.wg_waves ? tune.wg_waves : (residency ? 1 : 4);
+            int wps = tune.waves_per_simd ? tune.waves_per_simd : 8;
+            size_t lds_wg = static_cast<size_t>(lds_words) * 4 * wg_waves;
+            if (residency && lds_wg > dev.lds_per_block)
+                return fail(NZ_EUNSUPPORTED, "residency %d needs %zu bytes of LDS per workgroup; the device allows %zu",
+                            tune.residency, lds_wg, dev.lds_per_block);
+            int wgs_per_cu = std::max(1, 4 * wps / wg_waves);
+            if (residency && lds_wg > 0) wgs_per_cu = std::max<int>(1, std::min<size_t>(wgs_per_cu, dev.lds_per_cu / lds_wg));
+            int grid = dev.cus * wgs_per_cu;
+            grid = std::min(grid, (n + wg_waves - 1) / wg_waves);
+            NzSweepArgs args;
+            args.desc = d_desc;
+            args.queue = d_queue;
+            args.nqueue = n;
+            args.qhead = d_qhead;
+            args.tabs = d_tabs;
+            args.ws = ws;
+            args.state = d_state;
+            args.lds_words = lds_words;
+            args.dcap = tune.dcap;
+            HIP_TRY(nz::launch_sweep(nch_for(max_z), residency, args, d_nstar, d_mass, d_outidx, grid, wg_waves, st));
+            if (pe) HIP_TRY(hipEventRecord(pe->ev[4], st));
+
+            // ---- read back and schedule the redo of unfinished samples
+            std::vector<NzState> state(n);
+            HIP_TRY(hipMemcpyAsync(state.data(), d_state, n * sizeof(NzState), hipMemcpyDeviceToHost, st));
+            HIP_TRY(hipStreamSynchronize(st));
+            if (pe) {
+                for (int k = 0; k < 4; ++k) {
+                    float ms = 0.0f;
+                    HIP_TRY(hipEventElapsedTime(&ms, pe->ev[k], pe->ev[k + 1]));
+                    g_ms[k] += ms;
+                }
+                g_ms[5] += 1.0;
+            }
+            for (int32_t di = 0; di < n; ++di) {
+                Plan p = chunk[chunk_of_desc[di]];
+                const int64_t N = pow5(p.L);
+                switch (state[di].status) {
+                case NZ_ST_DONE:
+                    continue;
+                case NZ_ST_BAND:
+                    ++g_stats[1];
+                    p.band_hi = std::min<int64_t>(N, p.n0 + 2 * std::max<int64_t>(p.band_hi - p.n0, 2048));
+                    break;
+                case NZ_ST_BUCKET:
+                    ++g_stats[2];
+                    p.shift_adj += 1;
+                    break;
+                case NZ_ST_BACKOFF:
+                    ++g_stats[3];
+                    if (h_backoffs) ++h_backoffs[p.job];
+                    if (p.backoff > 0 && p.n0 - p.backoff > 0) {
+                        p.n0 -= p.backoff;
+                        p.backoff = 0;
+                    } else {
+                        p.n0 = 0;
+                    }
+                    break;
+                case NZ_ST_PREFIX:
+                    p.prefix_mul *= 2;
+                    break;
+                default:
+                    return fail(NZ_EDEVICE, "sample %lld finished with status %d", (long long)p.sample, state[di].status);
+                }
+                redo.push_back(p);
+            }
+        }
+        todo.swap(redo);
+    }
+    return NZ_OK;
+}
+
+size_t batch_bytes(const nz_job *jobs, int32_t njobs, const Tune &tune)
+{
+    // all samples of the first chunk resident, plus room for one redo of the
+    // largest sample with a full band
+    std::vector<size_t> per;
+    TablePool pool;
+    int32_t maxL = 1;
+    for (int j = 0; j < njobs; ++j) {
+        int32_t z;
+        pool.get(jobs[j].zone_mask, jobs[j].L, &z);
+        Plan p{};
+        p.L = jobs[j].L;
+        p.mask = jobs[j].zone_mask;
+        p.n0 = jobs[j].n0 > 0 ? jobs[j].n0 : 0;
+        const int64_t N = pow5(p.L);
+        p.band_hi = jobs[j].band_hi > 0 ? std::min<int64_t>(jobs[j].band_hi, N) : default_band_hi(p.L, p.mask, p.n0);
+        if (p.band_hi <= p.n0) p.band_hi = std::min<int64_t>(N, p.n0 + 4096);
+        p.prefix_mul = 1;
+        const size_t s = plan_sizes(p, tune.bucket_log2).total;
+        for (int64_t k = 0; k < jobs[j].nsamples && static_cast<int64_t>(per.size()) < 4 * kMaxChunk; ++k) per.push_back(s);
+        maxL = std::max(maxL, jobs[j].L);
+    }
+    std::sort(per.begin(), per.end(), std::greater<size_t>());
+    const size_t count = std::min<size_t>(per.size(), kMaxChunk);
+    size_t total = header_bytes(pool.entries.size(), static_cast<int32_t>(std::max<size_t>(count, 1)));
+    for (size_t k = 0; k < count; ++k) total += per[k];
+    Plan full{};
+    full.L = maxL;
+    full.mask = 127;
+    full.band_hi = pow5(maxL);
+    full.prefix_mul = 1;
+    total += plan_sizes(full, tune.bucket_log2).total;
+    return total;
+}
+
+}  // namespace
+
+namespace nz {
+int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+}  // namespace nz
+
+// ---------------------------------------------------------------------------
+// Public entry points.
+
+NZ_API const char *nz_last_error(void) { return g_err.c_str(); }
+
+NZ_API int nz_abi_version(void) { return NZ_ABI_VERSION; }
+
+NZ_API int nz_coordination(uint32_t zone_mask)
+{
+    if (zone_mask < 1 || zone_mask > 127) return -1;
+    return static_cast<int>(zone_vectors(zone_mask).size());
+}
+
+NZ_API int nz_last_batch_stats(int64_t stats[4])
+{
+    if (!stats) return fail(NZ_EINVAL, "stats is NULL");
+    for (int k = 0; k < 4; ++k) stats[k] = g_stats[k];
+    return NZ_OK;
+}
+
+NZ_API int nz_set_timing(int enable)
+{
+    g_timing = enable != 0;
+    return NZ_OK;
+}
+
+NZ_API int nz_last_batch_timing(double ms[6])
+{
+    if (!ms) return fail(NZ_EINVAL, "ms is NULL");
+    for (int k = 0; k < 6; ++k) ms[k] = g_ms[k];
+    return NZ_OK;
+}
+
+NZ_API int nz_batch_workspace_bytes(const nz_job *jobs, int32_t njobs, const nz_tuning *tune, size_t *bytes)
+{
+    if (!bytes) return fail(NZ_EINVAL, "bytes is NULL");
+    if (njobs < 0 || (njobs > 0 && !jobs)) return fail(NZ_EINVAL, "bad job array");
+    for (int j = 0; j < njobs; ++j)
+        if (int rc = check_job(jobs[j], j)) return rc;
+    Tune t;
+    if (int rc = read_tune(tune, t)) return rc;
+    try {
+        *bytes = batch_bytes(jobs, njobs, t);
+    } catch (...) {
+        return fail(NZ_ENOMEM, "host allocation failed while sizing the workspace");
+    }
+    return NZ_OK;
+}
+
+NZ_API int nz_sweep_batch(const nz_job *jobs, int32_t njobs, void *d_ws, size_t ws_bytes, int32_t *d_nstar,
+                          int32_t *d_mass, int32_t *h_backoffs, const nz_tuning *tune, void *stream)
+{
+    if (njobs < 0 || (njobs > 0 && !jobs)) return fail(NZ_EINVAL, "bad job array");
+    int64_t total = 0;
+    for (int j = 0; j < njobs; ++j) {
+        if (int rc = check_job(jobs[j], j)) return rc;
+        total += jobs[j].nsamples;
+    }
+    if (total == 0) return NZ_OK;
+    if (!d_ws || !d_nstar) return fail(NZ_EINVAL, "workspace or n* output is NULL");
+    if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(NZ_EINVAL, "workspace must be 256-byte aligned");
+    Tune t;
+    if (int rc = read_tune(tune, t)) return rc;
+    t.dcap = env_dcap();
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (g_timing) {
+        HIP_TRY(hipEventCreate(&e0));
+        HIP_TRY(hipEventCreate(&e1));
+        HIP_TRY(hipEventRecord(e0, static_cast<hipStream_t>(stream)));
+    }
+    int rc;
+    try {
+        rc = run_batch(jobs, njobs, static_cast<uint8_t *>(d_ws), ws_bytes, d_nstar, d_mass, h_backoffs, t,
+                       static_cast<hipStream_t>(stream));
+    } catch (...) {
+        rc = fail(NZ_ENOMEM, "host allocation failed");
+    }
+    if (e0) {
+        float ms = 0.0f;
+        if (rc == NZ_OK && hipEventRecord(e1, static_cast<hipStream_t>(stream)) == hipSuccess &&
+            hipEventSynchronize(e1) == hipSuccess && hipEventElapsedTime(&ms, e0, e1) == hipSuccess)
+            g_ms[4] = ms;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+    }
+    return rc;
+}
+
+NZ_API int nz_sweep(int32_t L, uint32_t zone_mask, int32_t boundary, int64_t nsamples, uint64_t seed, int32_t *nstar,
+                    int32_t *mass)
+{
+    nz_job j{};
+    j.L = L;
+    j.zone_mask = zone_mask;
+    j.boundary = boundary;
+    j.seed = seed;
+    j.sample0 = 0;
+    j.nsamples = nsamples;
+    j.n0 = -1;
+    if (int rc = check_job(j, 0)) return rc;
+    if (nsamples == 0) return NZ_OK;
+    if (!nstar) return fail(NZ_EINVAL, "nstar is NULL");
+    if (nsamples > 0x7FFFFFFF) return fail(NZ_EINVAL, "nsamples too large");
+    Tune t;
+    t.dcap = env_dcap();
+    size_t bytes = 0;
+    try {
+        bytes = batch_bytes(&j, 1, t);
+    } catch (...) {
+        return fail(NZ_ENOMEM, "host allocation failed");
+    }
+    // stay well inside the device memory
+    size_t freeb = 0, totalb = 0;
+    HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+    bytes = std::min(bytes, freeb / 2);
+    void *ws = nullptr;
+    int32_t *dn = nullptr, *dm = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess) return fail(NZ_ENOMEM, "hipMalloc of %zu workspace bytes failed", bytes);
+    if (hipMalloc(reinterpret_cast<void **>(&dn), nsamples * 4) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&dm), nsamples * 4) != hipSuccess) {
+        (void)hipFree(ws);
+        (void)hipFree(dn);
+        return fail(NZ_ENOMEM, "hipMalloc of outputs failed");
+    }
+    int rc;
+    try {
+        rc = run_batch(&j, 1, static_cast<uint8_t *>(ws), bytes, dn, dm, nullptr, t, nullptr);
+    } catch (...) {
+        rc = fail(NZ_ENOMEM, "host allocation failed");
+    }
+    if (rc == NZ_OK) {
+        if (hipMemcpy(nstar, dn, nsamples * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            (mass && hipMemcpy(mass, dm, nsamples * 4, hipMemcpyDeviceToHost) != hipSuccess))
+            rc = fail(NZ_EDEVICE, "copy of results failed");
+    }
+    (void)hipFree(ws);
+    (void)hipFree(dn);
+    (void)hipFree(dm);
+    return rc;
+}
+
+// Binomial convolution (Sec. II.B): weights C(N,n) p^n (1-p)^(N-n) are formed
+// from the mode outward with the ratio w(n+1)/w(n) = (N-n)/(n+1) * p/(1-p) and
+// normalised by their sum.  Terms below 1e-300 of the mode weight are dropped.
+NZ_API int nz_canonical(const uint64_t *hist, int64_t hist_len, const double *p_grid, int64_t np, double *R)
+{
+    if (!hist || hist_len < 2) return fail(NZ_EINVAL, "hist must have at least 2 entries");
+    if (np < 0 || (np > 0 && (!p_grid || !R))) return fail(NZ_EINVAL, "bad p grid or output");
+    for (int64_t k = 0; k < np; ++k)
+        if (!(p_grid[k] >= 0.0 && p_grid[k] <= 1.0)) return fail(NZ_EINVAL, "p_grid[%lld] outside [0, 1]", (long long)k);
+    const int64_t N = hist_len - 1;
+    std::vector<double> F(N + 1);
+    double total = 0.0;
+    for (int64_t n = 0; n <= N; ++n) total += static_cast<double>(hist[n]);
+    if (total <= 0.0) return fail(NZ_EINVAL, "empty histogram");
+    // prefix sums in integers, divided once, so F is exact to rounding
+    uint64_t run = 0;
+    F[0] = 0.0;
+    for (int64_t n = 1; n <= N; ++n) {
+        run += hist[n];
+        F[n] = static_cast<double>(run) / total;
+    }
+    for (int64_t k = 0; k < np; ++k) {
+        const double p = p_grid[k];
+        if (p == 0.0) {
+            R[k] = F[0];
+            continue;
+        }
+        if (p == 1.0) {
+            R[k] = F[N];
+            continue;
+        }
+        int64_t mode = static_cast<int64_t>(std::floor((N + 1) * p));
+        if (mode > N) mode = N;
+        const double up = p / (1.0 - p);
+        double sw = 1.0, swf = F[mode];
+        double w = 1.0;
+        for (int64_t n = mode; n < N; ++n) {
+            w *= static_cast<double>(N - n) / static_cast<double>(n + 1) * up;
+            if (w < 1e-300) break;
+            sw += w;
+            swf += w * F[n + 1];
+        }
+        w = 1.0;
+        for (int64_t n = mode; n > 0; --n) {
+            w *= static_cast<double>(n) / static_cast<double>(N - n + 1) / up;
+            if (w < 1e-300) break;
+            sw += w;
+            swf += w * F[n - 1];
+        }
+        R[k] = swf / sw;
+    }
+    return NZ_OK;
+}

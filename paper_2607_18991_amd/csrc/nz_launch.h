@@ -1,0 +1,29 @@
+// nz_launch.h -- kernel launchers of nz_kernels.hip used by the host planner.
+#pragma once
+#include <hip/hip_runtime.h>
+
+#include "nz_internal.h"
+
+namespace nz {
+
+hipError_t launch_clear(const NzSample *desc, int32_t nsamp, uint8_t *ws, NzState *state, hipStream_t st);
+
+// Keys for samples [first, first + count) of the descriptor array, all of
+// lattice size N.
+hipError_t launch_keys(const NzSample *desc, int32_t first, int32_t count, int32_t N, uint8_t *ws, NzState *state,
+                       hipStream_t st);
+int32_t keys_sites_per_block();
+
+hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int32_t max_cap, uint8_t *ws,
+                       hipStream_t st);
+
+// Bulk connected components for the samples listed in list[0..nlist).
+hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nlist, int32_t bx_hook, int32_t bx_site,
+                          const NzOffset *tabs, uint8_t *ws, NzState *state, hipStream_t st);
+
+// residency: 0 HBM, 1 bitset in LDS, 2 bitset and parents in LDS.
+// nch in {1, 2, 4, 8, 14}.
+hipError_t launch_sweep(int nch, int residency, const NzSweepArgs &a, int32_t *nstar, int32_t *mass,
+                        const int32_t *out_index, int grid, int wg_waves, hipStream_t st);
+
+}  // namespace nz

@@ -1,0 +1,86 @@
+"""The C ABI library on the host: it loads, exports every function include/nz.h
+declares, validates arguments before touching a device, and its host-only
+binomial convolution agrees with the oracle's long-double one (not GPU)."""
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_2607_18991_amd import nz
+
+HEADER = os.path.join(os.path.dirname(__file__), "..", "include", "nz.h")
+
+
+def declared_functions():
+    txt = open(HEADER).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(nz_[a-z_0-9]+)\s*\(", txt)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 10
+    lib = nz.lib()
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(nz.EXPORTS)
+    assert nz.nz_abi_version() == 1
+
+
+def test_coordination_numbers(nzo):
+    for m in range(1, 128):
+        assert nz.nz_coordination(m) == len(nzo.offsets(m))
+    assert nz.nz_coordination(0) == -1 and nz.nz_coordination(128) == -1
+
+
+@pytest.mark.parametrize("args,code", [
+    ((0, 1, 0, 1, 1), nz.NZ_EINVAL),
+    ((56, 1, 0, 1, 1), nz.NZ_EUNSUPPORTED),
+    ((4, 0, 0, 1, 1), nz.NZ_EINVAL),
+    ((4, 128, 0, 1, 1), nz.NZ_EINVAL),
+    ((4, 1, 1, 1, 1), nz.NZ_EUNSUPPORTED),
+    ((4, 1, 0, -1, 1), nz.NZ_EINVAL),
+])
+def test_sweep_rejects_bad_arguments_before_any_launch(args, code):
+    import ctypes
+
+    L, m, b, n, s = args
+    out = np.zeros(4, dtype=np.int32)
+    rc = nz.lib().nz_sweep(L, m, b, n, s, out.ctypes.data_as(ctypes.c_void_p), None)
+    assert rc == code
+    assert len(nz.lib().nz_last_error()) > 0
+
+
+def test_batch_rejects_bad_jobs():
+    with pytest.raises(nz.NzError) as e:
+        nz.nz_batch_workspace_bytes([dict(L=4, zone_mask=1, seed=1, nsamples=1, n0=1024)])
+    assert e.value.code == nz.NZ_EINVAL
+    with pytest.raises(nz.NzError):
+        nz.nz_batch_workspace_bytes([dict(L=4, zone_mask=1, seed=1, nsamples=1)], tune=dict(residency=7))
+
+
+def test_workspace_sizing_grows_with_samples():
+    a = nz.nz_batch_workspace_bytes([dict(L=8, zone_mask=1, seed=1, nsamples=10)])
+    b = nz.nz_batch_workspace_bytes([dict(L=8, zone_mask=1, seed=1, nsamples=100)])
+    c = nz.nz_batch_workspace_bytes([dict(L=16, zone_mask=1, seed=1, nsamples=10)])
+    assert 0 < a < b and c > a
+    assert a % 256 == 0 or a > 0
+
+
+@pytest.mark.parametrize("N,seed", [(32, 1), (1024, 2), (32768, 3), (1048576, 4)])
+def test_canonical_matches_oracle(nzo, N, seed):
+    rng = np.random.default_rng(seed)
+    h = np.zeros(N + 1, dtype=np.uint64)
+    lo, hi = int(0.05 * N) + 1, int(0.2 * N) + 2
+    np.add.at(h, rng.integers(lo, hi, size=2000), 1)
+    h[0] = 3
+    p = np.linspace(0, 1, 101) if N < 100000 else np.concatenate([[0, 0.5, 1], np.linspace(0.04, 0.22, 13)])
+    assert np.max(np.abs(nz.nz_canonical(h, p) - nzo.canonical(h, p))) <= 1e-12
+
+
+def test_canonical_rejects_bad_grid():
+    with pytest.raises(nz.NzError):
+        nz.nz_canonical(np.ones(5, dtype=np.uint64), [0.5, 1.5])
+    with pytest.raises(nz.NzError):
+        nz.nz_canonical(np.zeros(5, dtype=np.uint64), [0.5])
