@@ -217,9 +217,13 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
     int cap = static_cast<int>(std::ceil(mean + 8.0 * std::sqrt(mean) + 16.0));
     cap = (cap + 15) / 16 * 16;
     s.cap = std::max(16, std::min(cap, 4096));
+    // test hooks: tiny buckets / prefill lists force the redo paths
+    if (const char *e = getenv("NZ_DEBUG_BUCKET_CAP")) s.cap = std::max(1, std::min(4096, atoi(e)));
     if (p.n0 > 0) {
         const double e = static_cast<double>(p.n0);
-        s.prefix_cap = static_cast<int32_t>(std::min<double>(static_cast<double>(N), (e + 8.0 * std::sqrt(e) + 64.0) * p.prefix_mul));
+        double want = e + 8.0 * std::sqrt(e) + 64.0;
+        if (const char *dbg = getenv("NZ_DEBUG_PREFIX_CAP")) want = std::max(1, atoi(dbg));
+        s.prefix_cap = static_cast<int32_t>(std::min<double>(static_cast<double>(N), want * p.prefix_mul));
     } else {
         s.prefix_cap = 0;
     }

@@ -328,9 +328,19 @@ __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__rest
     if (n0 > d.prefix_cap) return;
     int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
+    // Each thread writes only its own entry and walks the forest read-only: a
+    // halving write here could replace an entry that another thread has
+    // already pointed at its root with a non-root ancestor, and the size pass
+    // below relies on every member pointing straight at its root.  Roots do
+    // not change during this kernel, so every walk ends at the final root.
     for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n0; k += gridDim.x * blockDim.x) {
         const int32_t s = static_cast<int32_t>(prefix[k]);
-        const int32_t r = cc_find(par, s);
+        int32_t r = s;
+        int32_t p = ld_a(&par[r]);
+        while (p != r) {
+            r = p;
+            p = ld_a(&par[r]);
+        }
         st_a(&par[s], r);
     }
 }
