@@ -2,13 +2,15 @@
 
 Workload (the headline metric): L = 16 (1,048,576 sites), the seven compact
 neighbourhoods sc(5)-1 .. sc(5)-1,...,7 (zone masks 0x01 .. 0x7F), 1000 samples
-each, free boundaries, spanning along axis 0.  One step = one nz_sweep_batch
-call over all 7000 samples: Philox keys, key-band bucketing and sorting, the
-bulk connected-components prefill (learned mode), and the persistent sweep.
+each, free boundaries, spanning along axis 0.  One step = the whole path over
+all 7000 samples: MLP inference (learned mode), Philox keys, key-band
+bucketing and sorting, bulk connected-components prefill (learned mode) and the
+persistent sequential sweep, with n* and mass of every sample in HBM at the end.
 
-Printed: one JSON line.  value = site additions per second of the learned
-prefill path (sum of n* over samples / wall time; prefilled sites count as
-additions); also samples/s, the plain path's numbers and the speedup.
+Both modes are timed on the same samples; their outputs must be identical.
+value = site additions per second of the learned-prefill path (sum of n* over
+samples / wall time; prefilled sites count as additions, so both modes do the
+same additions and the speedup is a time ratio).
 """
 from __future__ import annotations
 
@@ -24,55 +26,76 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 COMPACT = [0x01, 0x03, 0x07, 0x0F, 0x1F, 0x3F, 0x7F]
-SEED = 0x5EED0016
+SEEDS = {16: 0x5EED1016, 24: 0x5EED1024}
 HBM_PEAK_GBS = 8000.0
 
 
 def bytes_per_addition(z: int) -> float:
-    """Algorithmic HBM bytes one site addition must move: the site id (4), the z
-    occupancy bits (z/8) and its own bit, its root word (4), two parent reads
-    per occupied neighbour find (about 0.8 neighbours -> 8 B each), and a root
-    read-modify-write per union (8)."""
+    """Algorithmic HBM bytes of one sequential site addition: the site (4 B), z
+    occupancy bits and its own word (z/8 + 4), its parent entry (4), about two
+    parent reads per occupied-neighbour find (8 per neighbour, ~0.8 neighbours on
+    average below the threshold) and a root read-modify-write per union (8)."""
     return 22.0 + z / 8.0
 
 
-def make_jobs(L, samples, n0_by_mask=None, sigma_by_mask=None, band_by_mask=None):
-    jobs = []
-    for m in COMPACT:
-        j = dict(L=L, zone_mask=m, seed=SEED, nsamples=samples)
-        if n0_by_mask is not None:
-            j["n0"] = int(n0_by_mask[m])
-            j["backoff"] = int(sigma_by_mask[m])
-        if band_by_mask is not None:
-            j["band_hi"] = int(band_by_mask[m])
-        jobs.append(j)
-    return jobs
+def base_jobs(L, samples):
+    return [dict(L=L, zone_mask=m, seed=SEEDS.get(L, 0x5EED0000 + L), nsamples=samples) for m in COMPACT]
 
 
-def run_steps(nz, torch, jobs, steps, warmup, tune=None):
+def run_mode(nz, torch, make_jobs, steps, warmup):
+    """make_jobs() is called inside every step (it runs the MLP in learned mode)."""
+    jobs = make_jobs()
     total = sum(j["nsamples"] for j in jobs)
-    ws = torch.empty(nz.nz_batch_workspace_bytes(jobs, tune), dtype=torch.uint8, device="cuda")
+    ws_bytes = nz.nz_batch_workspace_bytes(jobs)
+    ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     dn = torch.zeros(total, dtype=torch.int32, device="cuda")
     dm = torch.zeros(total, dtype=torch.int32, device="cuda")
     for _ in range(warmup):
-        nz.nz_sweep_batch(jobs, ws, dn, dm, tune=tune)
+        nz.nz_sweep_batch(make_jobs(), ws, dn, dm)
     torch.cuda.synchronize()
     nz.nz_set_timing(True)
     phase = {"keys_ms": 0.0, "cc_ms": 0.0, "sort_ms": 0.0, "sweep_ms": 0.0, "total_ms": 0.0, "sweep_launches": 0}
-    backoffs = 0
+    stats = {}
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        back = nz.nz_sweep_batch(jobs, ws, dn, dm, tune=tune)
-        backoffs += int(back.sum())
+        nz.nz_sweep_batch(make_jobs(), ws, dn, dm)
         t = nz.nz_last_batch_timing()
         for k in phase:
             phase[k] += t[k]
+        for k, v in nz.nz_last_batch_stats().items():
+            stats[k] = stats.get(k, 0) + v
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     nz.nz_set_timing(False)
     del ws
-    return wall, dn.cpu().numpy(), dm.cpu().numpy(), phase, backoffs
+    return {"wall": wall, "ns": dn.cpu().numpy(), "ms": dm.cpu().numpy(), "phase": phase, "stats": stats,
+            "jobs": jobs}
+
+
+def summarise(res, steps, S, z):
+    ms_step = res["wall"] / steps * 1e3
+    adds = int(res["ns"].astype(np.int64).sum())
+    serial = res["stats"]["serial_steps"] / steps
+    alg_bytes = 0.0
+    # serial steps per mask are not reported separately; weight by each mask's share of n*
+    share = np.array([res["ns"][k * S:(k + 1) * S].astype(np.float64).sum() for k in range(len(COMPACT))])
+    share = share / share.sum()
+    for k, m in enumerate(COMPACT):
+        alg_bytes += serial * share[k] * bytes_per_addition(z[m])
+    launches = max(res["phase"]["sweep_launches"], 1)
+    sweep_ms = res["phase"]["sweep_ms"] / launches
+    return {
+        "ms_per_step": ms_step,
+        "site_additions_per_s": adds / (ms_step / 1e3),
+        "samples_per_s": len(res["ns"]) / (ms_step / 1e3),
+        "sequential_steps_per_step": serial,
+        "prefilled_sites_per_step": res["stats"]["prefilled_sites"] / steps,
+        "backoffs_per_step": res["stats"]["backoffs"] / steps,
+        "phase_ms_per_step": {k: v / steps for k, v in res["phase"].items() if k != "sweep_launches"},
+        "sweep_kernel_ms": sweep_ms,
+        "sweep_alg_bytes": alg_bytes,
+    }
 
 
 def cpu_baseline(jobs, per_mask):
@@ -80,8 +103,8 @@ def cpu_baseline(jobs, per_mask):
 
     threads = max(1, min(os.cpu_count() or 1, 64))
     adds = 0
-    t0 = time.perf_counter()
     res = {}
+    t0 = time.perf_counter()
     for j in jobs:
         ns, ms = oracle.sweep_many(j["L"], j["zone_mask"], j["seed"], 0, per_mask, nthreads=threads)
         res[j["zone_mask"]] = (ns, ms)
@@ -98,63 +121,84 @@ def main():
     ap.add_argument("--L", type=int, default=16)
     ap.add_argument("--samples", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--residency", type=int, default=0)
+    ap.add_argument("--l24-samples", type=int, default=200, help="samples per mask of the L=24 table (0: skip)")
+    ap.add_argument("--mode", choices=["both", "learned", "plain"], default="both",
+                    help="profiling aid: run only one path (the JSON line then reports that path)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU; samples are independent and would be "
-                                   "split by sample range across GPUs (see the design notes)"}))
+        print(json.dumps({"error": "this build measures one GPU; samples are independent and shard by sample "
+                                   "range across GPUs, which is not run here"}), flush=True)
         sys.exit(2)
 
     import torch
 
-    from paper_2607_18991_amd import nz
+    from paper_2607_18991_amd import learned, nz
 
     torch.cuda.set_device(0)
     L, S = args.L, args.samples
     N = L**5
-    tune = dict(residency=args.residency) if args.residency else None
-    plain_jobs = make_jobs(L, S)
-    wall, ns, ms, phase, _ = run_steps(nz, torch, plain_jobs, args.steps, args.warmup, tune)
-    adds = int(ns.astype(np.int64).sum())
-    ms_step = wall / args.steps * 1e3
-    value = adds / (ms_step / 1e3)
-    samples_s = len(ns) / (ms_step / 1e3)
-
+    model = learned.PrefillModel.load()
+    jobs0 = base_jobs(L, S)
     z = {m: nz.nz_coordination(m) for m in COMPACT}
-    alg_bytes = 0.0
-    for k, m in enumerate(COMPACT):
-        alg_bytes += float(ns[k * S:(k + 1) * S].astype(np.int64).sum()) * bytes_per_addition(z[m])
-    sweep_ms = phase["sweep_ms"] / max(phase["sweep_launches"], 1)
-    achieved = alg_bytes / (sweep_ms / 1e3) / 1e9
 
+    if args.mode in ("both", "plain"):
+        plain = run_mode(nz, torch, lambda: learned.plan_band_only(model, jobs0), args.steps, args.warmup)
+    if args.mode in ("both", "learned"):
+        learn = run_mode(nz, torch, lambda: model.plan(jobs0), args.steps, args.warmup)
+    if args.mode == "plain":
+        learn = plain
+    elif args.mode == "learned":
+        plain = learn
+    identical = bool((plain["ns"] == learn["ns"]).all() and (plain["ms"] == learn["ms"]).all())
+    sp = summarise(plain, args.steps, S, z)
+    sl = summarise(learn, args.steps, S, z)
+
+    kernel_ms = sl["sweep_kernel_ms"]
+    achieved = sl["sweep_alg_bytes"] / (kernel_ms / 1e3) / 1e9
     out = {
         "metric": "site additions/s and samples/s at L=16, zones 1-7; learned-prefill vs plain speedup",
-        "value": value,
+        "value": sl["site_additions_per_s"],
         "unit": "site additions/s",
         "n_gpus": 1,
         "steps": args.steps,
         "warmup": args.warmup,
-        "ms_per_step": ms_step,
+        "ms_per_step": sl["ms_per_step"],
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "int32",
         "data": "synthetic (Philox4x32-10 occupation orders)",
-        "config": {"workload": f"L={L} (N={N}), 7 compact zone masks x {S} samples, free boundaries, plain sweep",
-                   "L": L, "samples_per_mask": S, "masks": [hex(m) for m in COMPACT]},
-        "samples_per_s": samples_s,
-        "phase_ms_per_step": {k: (v / args.steps if k != "sweep_launches" else v) for k, v in phase.items()},
+        "config": {"workload": f"L={L} (N={N}) x 7 compact zone masks (0x01..0x7F) x {S} samples, free boundaries, "
+                               f"spanning along axis 0, learned prefill + persistent sweep",
+                   "L": L, "samples_per_mask": S},
+        "samples_per_s": sl["samples_per_s"],
+        "speedup_learned_vs_plain": sp["ms_per_step"] / sl["ms_per_step"],
+        "outputs_identical_plain_vs_learned": identical,
+        "learned": sl,
+        "plain": sp,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "nz_sweep_kernel", "kernel_ms": sweep_ms},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "nz_sweep_kernel",
+                     "kernel_ms": kernel_ms},
     }
+    if args.l24_samples > 0:
+        # the same comparison at L = 24 (7,962,624 sites), one timed step per mode
+        j24 = base_jobs(24, args.l24_samples)
+        p24 = run_mode(nz, torch, lambda: learned.plan_band_only(model, j24), 1, 0)
+        l24 = run_mode(nz, torch, lambda: model.plan(j24), 1, 0)
+        s24p, s24l = summarise(p24, 1, args.l24_samples, z), summarise(l24, 1, args.l24_samples, z)
+        out["L24"] = {"samples_per_mask": args.l24_samples,
+                      "outputs_identical_plain_vs_learned": bool((p24["ns"] == l24["ns"]).all() and
+                                                                 (p24["ms"] == l24["ms"]).all()),
+                      "speedup_learned_vs_plain": s24p["ms_per_step"] / s24l["ms_per_step"],
+                      "learned": s24l, "plain": s24p}
     if not args.no_cpu:
         per = 4 if L >= 16 else 32
-        cpu_rate, threads, res = cpu_baseline(plain_jobs, per)
-        parity = all((res[m][0] == ns[k * S:k * S + per]).all() and (res[m][1] == ms[k * S:k * S + per]).all()
-                     for k, m in enumerate(COMPACT))
+        cpu_rate, threads, res = cpu_baseline(jobs0, per)
+        parity = all((res[m][0] == learn["ns"][k * S:k * S + per]).all() and
+                     (res[m][1] == learn["ms"][k * S:k * S + per]).all() for k, m in enumerate(COMPACT))
         out["cpu_baseline"] = {"value": cpu_rate, "unit": "site additions/s", "cores": threads, "kind": "oracle",
-                               "sample": f"first {per} samples of each of the 7 masks at L={L}"}
+                               "sample": f"samples 0..{per - 1} of each of the 7 masks at L={L}, one sample per "
+                                         f"thread (keys, full sort, serial union-find)"}
         out["parity_on_cpu_sample"] = bool(parity)
     print(json.dumps(out), flush=True)
 

@@ -91,9 +91,10 @@ int nz_canonical(const uint64_t *hist, int64_t hist_len, const double *p_grid, i
  *             floor(n0 / N * 2^64) is occupied at once and its clusters are
  *             labelled by parallel connected components; the sequential sweep
  *             continues from there.  If that bulk state already spans, the
- *             sample backs off to n0 - backoff (then to 0) and is redone, so n*
- *             and mass never depend on n0.
- *   backoff   sites to back off by on the first span at n0 (0: straight to 0).
+ *             sample backs off to n0 - backoff, then to successive halves of
+ *             that, then to 0 (below 64 sites), and is redone, so n* and mass
+ *             never depend on n0.
+ *   backoff   sites to back off by on the first span at n0 (0: halve at once).
  *   band_hi   expected upper bound on n* used to size the key band (sites;
  *             0: library default).  Never changes results, only work.
  *   prio      relative expected cost of a sample, for longest-first
@@ -151,10 +152,11 @@ int nz_sweep_batch(const nz_job *jobs, int32_t njobs, void *d_ws, size_t ws_byte
                    int32_t *d_nstar, int32_t *d_mass, int32_t *h_backoffs,
                    const nz_tuning *tune, void *stream);
 
-/* Statistics of the last nz_sweep_batch on the calling thread: chunks, samples
- * redone because their band ran out, because a bucket overflowed, and backoffs.
- * stats[0..3]; returns NZ_OK. */
-int nz_last_batch_stats(int64_t stats[4]);
+/* Statistics of the last nz_sweep_batch on the calling thread, stats[0..5]:
+ * chunks, samples redone because their band ran out, because a bucket
+ * overflowed, backoffs, sites occupied by the bulk prefill (summed over the
+ * final runs of all samples) and sites added by the sequential sweep. */
+int nz_last_batch_stats(int64_t stats[6]);
 
 /* Phase timing of nz_sweep_batch with HIP events recorded on the caller's
  * stream around each group of launches.  nz_set_timing(1) turns it on for later
@@ -193,6 +195,13 @@ int nz_mlp_backward(const uint16_t *params_bf16, const float *x, const float *ac
                     const float *dy, float *grad, int32_t B, void *stream);
 int nz_mlp_adam(float *params_fp32, uint16_t *params_bf16, const float *grad, float *adam_m,
                 float *adam_v, const float hyper[5], int32_t step, void *stream);
+
+/* Weighted mean squared error of y against target over B rows and both outputs,
+ * sum_b w_b / sum(w) * sum_o (y - t)^2, into loss[0], and its gradient
+ * dy = 2 w_b / sum(w) * (y - t).  DEVICE pointers: y, target, dy float [B][2];
+ * weight float [B] (non-negative, positive sum); loss float [1]. */
+int nz_mlp_loss(const float *y, const float *target, const float *weight, float *dy, float *loss,
+                int32_t B, void *stream);
 
 #ifdef __cplusplus
 }

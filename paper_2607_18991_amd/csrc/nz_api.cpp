@@ -24,7 +24,7 @@
 namespace {
 
 thread_local std::string g_err = "no error";
-thread_local int64_t g_stats[4] = {0, 0, 0, 0};
+thread_local int64_t g_stats[6] = {0, 0, 0, 0, 0, 0};
 thread_local bool g_timing = false;
 thread_local double g_ms[6] = {0, 0, 0, 0, 0, 0};
 
@@ -97,6 +97,17 @@ std::vector<std::array<int, 5>> zone_vectors(uint32_t mask)
     std::vector<std::array<int, 5>> all = neg;
     for (const auto &d : neg) all.push_back({-d[0], -d[1], -d[2], -d[3], -d[4]});
     return all;
+}
+
+// z(mask) for every mask, enumerated once.
+int coordination(uint32_t mask)
+{
+    static const std::array<int, 128> z = [] {
+        std::array<int, 128> t{};
+        for (uint32_t m = 1; m < 128; ++m) t[m] = static_cast<int>(zone_vectors(m).size());
+        return t;
+    }();
+    return mask >= 1 && mask <= 127 ? z[mask] : -1;
 }
 
 std::vector<NzOffset> build_table(uint32_t mask, int32_t L)
@@ -241,7 +252,7 @@ int64_t default_band_hi(int32_t L, uint32_t mask, int64_t n0)
 {
     const int64_t N = pow5(L);
     if (N <= 8192) return N;
-    const int z = static_cast<int>(zone_vectors(mask).size());
+    const int z = coordination(mask);
     const double frac = pc_prior(z) * (1.0 + 4.0 / std::sqrt(static_cast<double>(L)));
     int64_t hi = static_cast<int64_t>(frac * N) + 4096;
     hi = std::max(hi, n0 + 4096);
@@ -322,7 +333,7 @@ struct TablePool {
         auto key = std::make_pair(mask, L);
         auto it = index.find(key);
         if (it != index.end()) {
-            *z = static_cast<int32_t>(zone_vectors(mask).size());
+            *z = coordination(mask);
             return it->second;
         }
         auto t = build_table(mask, L);
@@ -339,7 +350,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
 {
     Device dev;
     if (int rc = device_info(dev)) return rc;
-    for (int k = 0; k < 4; ++k) g_stats[k] = 0;
+    for (int k = 0; k < 6; ++k) g_stats[k] = 0;
     for (int k = 0; k < 6; ++k) g_ms[k] = 0.0;
     if (h_backoffs)
         for (int j = 0; j < njobs; ++j) h_backoffs[j] = 0;
@@ -548,6 +559,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 const int64_t N = pow5(p.L);
                 switch (state[di].status) {
                 case NZ_ST_DONE:
+                    g_stats[4] += state[di].n0;
+                    g_stats[5] += (state[di].nstar > 0 ? state[di].nstar : N) - state[di].n0;
                     continue;
                 case NZ_ST_BAND:
                     ++g_stats[1];
@@ -560,11 +573,15 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 case NZ_ST_BACKOFF:
                     ++g_stats[3];
                     if (h_backoffs) ++h_backoffs[p.job];
+                    // first back off by the caller's step, then halve: a badly
+                    // predicted lattice needs only a few rounds, and n0 reaches 0
+                    // after at most log2(N) of them
                     if (p.backoff > 0 && p.n0 - p.backoff > 0) {
                         p.n0 -= p.backoff;
                         p.backoff = 0;
                     } else {
-                        p.n0 = 0;
+                        p.backoff = 0;
+                        p.n0 = p.n0 >= 64 ? p.n0 / 2 : 0;
                     }
                     break;
                 case NZ_ST_PREFIX:
@@ -632,13 +649,13 @@ NZ_API int nz_abi_version(void) { return NZ_ABI_VERSION; }
 NZ_API int nz_coordination(uint32_t zone_mask)
 {
     if (zone_mask < 1 || zone_mask > 127) return -1;
-    return static_cast<int>(zone_vectors(zone_mask).size());
+    return coordination(zone_mask);
 }
 
-NZ_API int nz_last_batch_stats(int64_t stats[4])
+NZ_API int nz_last_batch_stats(int64_t stats[6])
 {
     if (!stats) return fail(NZ_EINVAL, "stats is NULL");
-    for (int k = 0; k < 4; ++k) stats[k] = g_stats[k];
+    for (int k = 0; k < 6; ++k) stats[k] = g_stats[k];
     return NZ_OK;
 }
 

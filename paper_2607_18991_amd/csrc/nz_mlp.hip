@@ -169,6 +169,40 @@ __global__ __launch_bounds__(256) void mlp_adam_kernel(float *__restrict__ w, ui
     wb[i] = f32_to_bf16(wi);
 }
 
+// Weighted squared error and its gradient; one workgroup, fixed summation order.
+__global__ __launch_bounds__(256) void mlp_loss_kernel(const float *__restrict__ y, const float *__restrict__ t,
+                                                       const float *__restrict__ w, float *__restrict__ dy,
+                                                       float *__restrict__ loss, int32_t B)
+{
+    __shared__ float red[256];
+    float sw = 0.0f;
+    for (int b = threadIdx.x; b < B; b += 256) sw += w[b];
+    red[threadIdx.x] = sw;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    const float inv = 1.0f / red[0];
+    __syncthreads();
+    float acc = 0.0f;
+    for (int b = threadIdx.x; b < B; b += 256) {
+        const float wn = w[b] * inv;
+        for (int o = 0; o < OUT; ++o) {
+            const float r = y[b * OUT + o] - t[b * OUT + o];
+            acc = fmaf(wn * r, r, acc);
+            dy[b * OUT + o] = 2.0f * wn * r;
+        }
+    }
+    red[threadIdx.x] = acc;
+    __syncthreads();
+    for (int s = 128; s > 0; s >>= 1) {
+        if (threadIdx.x < s) red[threadIdx.x] += red[threadIdx.x + s];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) loss[0] = red[0];
+}
+
 }  // namespace nzmlp
 
 namespace nz {
@@ -212,5 +246,15 @@ NZ_API int nz_mlp_adam(float *params_fp32, uint16_t *params_bf16, const float *g
     hipLaunchKernelGGL(nzmlp::mlp_adam_kernel, dim3((nzmlp::NPARAM + 255) / 256), dim3(256), 0,
                        static_cast<hipStream_t>(stream), params_fp32, params_bf16, grad, adam_m, adam_v, lr, b1, b2,
                        eps, wd, c1, c2);
+    return mlp_fail(hipGetLastError());
+}
+
+NZ_API int nz_mlp_loss(const float *y, const float *target, const float *weight, float *dy, float *loss, int32_t B,
+                       void *stream)
+{
+    if (!y || !target || !weight || !dy || !loss || B < 1)
+        return nz::set_error(NZ_EINVAL, "nz_mlp_loss: NULL pointer or B < 1");
+    hipLaunchKernelGGL(nzmlp::mlp_loss_kernel, dim3(1), dim3(256), 0, static_cast<hipStream_t>(stream), y, target,
+                       weight, dy, loss, B);
     return mlp_fail(hipGetLastError());
 }

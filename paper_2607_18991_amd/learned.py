@@ -1,0 +1,162 @@
+"""Learned prefill: a small MLP predicts, for a lattice (zone mask, L), the mean
+and the spread of n*/N; each sample then starts its Newman-Ziff sweep (Sec. II.B)
+from a bulk state with n0 = (mean - 3 std) N sites already occupied and
+labelled.  The prediction only moves work between the bulk and the sequential
+phase: a sample whose bulk state already spans backs off, so n* and the mass
+never depend on it.
+
+Every arithmetic step of training and inference runs in the MLP kernels of
+libnz (forward, loss, backward, Adam); PyTorch holds the device buffers.
+"""
+from __future__ import annotations
+
+import json
+import math
+import os
+
+import numpy as np
+
+from . import nz
+
+IN, H, OUT = 8, 64, 2
+DEFAULT_PATH = os.path.join(os.path.dirname(os.path.abspath(__file__)), "prefill_mlp.json")
+
+
+def zone_bits(mask: int) -> list[float]:
+    return [float((mask >> k) & 1) for k in range(7)]
+
+
+def to_bf16_bits(x32: np.ndarray) -> np.ndarray:
+    """float32 -> bfloat16 bit patterns, round to nearest even (host copy of the
+    rounding the Adam kernel applies on the device)."""
+    u = np.ascontiguousarray(x32, dtype=np.float32).view(np.uint32).astype(np.uint64)
+    lsb = (u >> np.uint64(16)) & np.uint64(1)
+    return ((u + np.uint64(0x7FFF) + lsb) >> np.uint64(16)).astype(np.uint16)
+
+
+def init_params(seed: int = 0) -> np.ndarray:
+    """Glorot-uniform weights, zero biases; float32 flat vector."""
+    rng = np.random.default_rng(seed)
+    parts = []
+    for fan_in, fan_out in ((IN, H), (H, H), (H, OUT)):
+        a = math.sqrt(6.0 / (fan_in + fan_out))
+        parts.append(rng.uniform(-a, a, size=fan_in * fan_out))
+        parts.append(np.zeros(fan_out))
+    flat = np.concatenate(parts).astype(np.float32)
+    assert flat.size == nz.NZ_MLP_NPARAM
+    return flat
+
+
+class PrefillModel:
+    def __init__(self, params: np.ndarray, lnL_mean: float, lnL_std: float, meta: dict | None = None):
+        self.params = np.asarray(params, dtype=np.float32)
+        self.lnL_mean = float(lnL_mean)
+        self.lnL_std = float(lnL_std)
+        self.meta = meta or {}
+
+    # ---------------------------------------------------------------- io
+    def save(self, path: str = DEFAULT_PATH) -> None:
+        with open(path, "w") as f:
+            json.dump({"lnL_mean": self.lnL_mean, "lnL_std": self.lnL_std, "meta": self.meta,
+                       "params_fp32": [float(v) for v in self.params]}, f)
+
+    @classmethod
+    def load(cls, path: str = DEFAULT_PATH) -> "PrefillModel":
+        with open(path) as f:
+            d = json.load(f)
+        return cls(np.array(d["params_fp32"], dtype=np.float32), d["lnL_mean"], d["lnL_std"], d.get("meta"))
+
+    # ---------------------------------------------------------------- inference
+    def features(self, masks, Ls) -> np.ndarray:
+        rows = [zone_bits(int(m)) + [(math.log(int(L)) - self.lnL_mean) / self.lnL_std] for m, L in zip(masks, Ls)]
+        return np.array(rows, dtype=np.float32).reshape(-1, IN)
+
+    def predict(self, masks, Ls, stream=None):
+        """Predicted (mean, std) of n*/N per (mask, L), via the forward kernel."""
+        import torch
+
+        x = torch.from_numpy(self.features(masks, Ls)).cuda()
+        pb = torch.from_numpy(to_bf16_bits(self.params).view(np.int16)).cuda()
+        B = x.shape[0]
+        y = torch.empty((B, OUT), dtype=torch.float32, device="cuda")
+        act = torch.empty((B, nz.NZ_MLP_NACT), dtype=torch.float32, device="cuda")
+        nz.nz_mlp_forward(pb, x, y, act, stream=stream)
+        out = y.cpu().numpy().astype(np.float64)
+        return np.exp(out[:, 0]), np.exp(out[:, 1])
+
+    def plan(self, jobs, k_sigma: float = 3.0, band_sigma: float = 8.0):
+        """Copies of the job dicts with the learned n0, backoff step and band."""
+        jobs = [dict(j) for j in jobs]
+        mean, std = self.predict([j["zone_mask"] for j in jobs], [j["L"] for j in jobs])
+        for j, mu, sd in zip(jobs, mean, std):
+            N = int(j["L"]) ** 5
+            n0 = int(math.floor((mu - k_sigma * sd) * N))
+            j["n0"] = max(0, min(N - 1, n0))
+            j["backoff"] = int(math.ceil(k_sigma * sd * N))
+            j["band_hi"] = min(N, int(math.ceil((mu + band_sigma * sd) * N)) + 1024)
+        return jobs
+
+
+def plan_band_only(model: PrefillModel, jobs, band_sigma: float = 8.0):
+    """Plain sweeps (no prefill) with the learned band size, so that plain and
+    learned runs differ only in the prefill."""
+    mean, std = model.predict([j["zone_mask"] for j in jobs], [j["L"] for j in jobs])
+    out = []
+    for j, mu, sd in zip(jobs, mean, std):
+        j = dict(j)
+        N = int(j["L"]) ** 5
+        j["n0"] = -1
+        j["band_hi"] = min(N, int(math.ceil((mu + band_sigma * sd) * N)) + 1024)
+        out.append(j)
+    return out
+
+
+def aggregate(L: int, mask: int, nstar: np.ndarray) -> dict:
+    """Training target of one lattice: ln mean and ln std of n*/N over samples
+    that span."""
+    N = L**5
+    f = nstar[nstar > 0].astype(np.float64) / N
+    sd = max(float(f.std()), 0.5 / N)
+    return {"L": L, "mask": mask, "count": int(len(f)), "mean": float(f.mean()), "std": sd}
+
+
+def train(points, steps: int = 3000, lr: float = 3e-3, seed: int = 0, log_every: int = 0,
+          wd: float = 0.0) -> PrefillModel:
+    """Fit the MLP to aggregates [{'L','mask','count','mean','std'}] with the
+    device kernels: forward, weighted squared error, backward, Adam."""
+    import torch
+
+    Ls = np.array([p["L"] for p in points], dtype=np.float64)
+    lnL = np.log(Ls)
+    w = np.array([p["count"] for p in points], dtype=np.float64)
+    lnL_mean = float(lnL.mean())
+    lnL_std = float(lnL.std()) if lnL.std() > 0 else 1.0
+    model = PrefillModel(init_params(seed), lnL_mean, lnL_std)
+    x = torch.from_numpy(model.features([p["mask"] for p in points], [p["L"] for p in points])).cuda()
+    tgt = torch.from_numpy(np.array([[math.log(p["mean"]), math.log(p["std"])] for p in points],
+                                    dtype=np.float32)).cuda()
+    # every lattice counts, with a mild preference for the better-sampled ones
+    wt = torch.from_numpy(np.sqrt(w).astype(np.float32)).cuda()
+    B = x.shape[0]
+    w32 = torch.from_numpy(model.params.copy()).cuda()
+    wb = torch.from_numpy(to_bf16_bits(model.params).view(np.int16)).cuda()
+    m = torch.zeros_like(w32)
+    v = torch.zeros_like(w32)
+    g = torch.zeros_like(w32)
+    y = torch.empty((B, OUT), dtype=torch.float32, device="cuda")
+    act = torch.empty((B, nz.NZ_MLP_NACT), dtype=torch.float32, device="cuda")
+    dy = torch.empty_like(y)
+    loss = torch.zeros(1, dtype=torch.float32, device="cuda")
+    hyper = [lr, 0.9, 0.999, 1e-8, wd]
+    history = []
+    for step in range(1, steps + 1):
+        nz.nz_mlp_forward(wb, x, y, act)
+        nz.nz_mlp_loss(y, tgt, wt, dy, loss)
+        nz.nz_mlp_backward(wb, x, act, dy, g)
+        nz.nz_mlp_adam(w32, wb, g, m, v, hyper, step)
+        if step == 1 or step == steps or (log_every and step % log_every == 0):
+            history.append((step, float(loss.item())))
+    model.params = w32.cpu().numpy()
+    model.meta = {"steps": steps, "lr": lr, "seed": seed, "loss_history": history,
+                  "points": len(points), "L_values": sorted(set(int(L) for L in Ls))}
+    return model

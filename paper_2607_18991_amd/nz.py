@@ -29,6 +29,7 @@ EXPORTS = (
     "nz_last_error", "nz_abi_version", "nz_coordination", "nz_sweep", "nz_canonical",
     "nz_batch_workspace_bytes", "nz_sweep_batch", "nz_last_batch_stats",
     "nz_mlp_forward", "nz_mlp_backward", "nz_mlp_adam", "nz_set_timing", "nz_last_batch_timing",
+    "nz_mlp_loss",
 )
 
 
@@ -93,6 +94,8 @@ def lib():
     L.nz_mlp_backward.restype = ctypes.c_int
     L.nz_mlp_adam.argtypes = [P, P, P, P, P, P, i32, P]
     L.nz_mlp_adam.restype = ctypes.c_int
+    L.nz_mlp_loss.argtypes = [P, P, P, P, P, i32, P]
+    L.nz_mlp_loss.restype = ctypes.c_int
     _lib = L
     return L
 
@@ -194,9 +197,10 @@ def nz_sweep_batch(jobs, ws, nstar, mass=None, tune=None, stream=None):
 
 
 def nz_last_batch_stats() -> dict:
-    s = np.zeros(4, dtype=np.int64)
+    s = np.zeros(6, dtype=np.int64)
     _check(lib().nz_last_batch_stats(_np_ptr(s)))
-    return {"chunks": int(s[0]), "band_redo": int(s[1]), "bucket_redo": int(s[2]), "backoffs": int(s[3])}
+    return {"chunks": int(s[0]), "band_redo": int(s[1]), "bucket_redo": int(s[2]), "backoffs": int(s[3]),
+            "prefilled_sites": int(s[4]), "serial_steps": int(s[5])}
 
 
 def nz_set_timing(enable: bool) -> None:
@@ -228,3 +232,9 @@ def nz_mlp_adam(params_fp32, params_bf16, grad, m, v, hyper, step: int, stream=N
     _check(lib().nz_mlp_adam(ctypes.c_void_p(params_fp32.data_ptr()), ctypes.c_void_p(params_bf16.data_ptr()),
                              ctypes.c_void_p(grad.data_ptr()), ctypes.c_void_p(m.data_ptr()),
                              ctypes.c_void_p(v.data_ptr()), _np_ptr(h), int(step), _stream_ptr(stream)))
+
+
+def nz_mlp_loss(y, target, weight, dy, loss, stream=None):
+    _check(lib().nz_mlp_loss(ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(target.data_ptr()),
+                             ctypes.c_void_p(weight.data_ptr()), ctypes.c_void_p(dy.data_ptr()),
+                             ctypes.c_void_p(loss.data_ptr()), y.shape[0], _stream_ptr(stream)))
