@@ -169,7 +169,9 @@ int nz_last_batch_timing(double ms[6]);
 /*
  * MLP that predicts the mean and spread of n* / N for the learned prefill: three dense
  * layers 8 -> 64 -> 64 -> 2 with tanh after the first two.  Inputs per row are
- * the seven zone-mask bits and a standardised ln L; outputs (u, v) estimate
+ * the seven zone-mask bits and a standardised size variable exp(-ln L / nu) =
+ * L^(-1/nu) (nu = 0.5720, the 5D correlation-length exponent of Sec. II.A.3);
+ * outputs (u, v) estimate
  * (ln mean, ln std) of n* / N.  Weights are BF16, arithmetic FP32.
  *
  * Parameter layout (NZ_MLP_NPARAM values, row-major, "in x out"):

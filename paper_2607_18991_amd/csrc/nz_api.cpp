@@ -198,6 +198,9 @@ uint64_t rank_to_key(int64_t n, int64_t N)
 struct Sizes {
     uint64_t T0;
     int32_t nb, cap, shift, full, prefix_cap;
+    int64_t n0b;      // prefill rank after a first backoff (0: none planned)
+    uint64_t T0b;     // its key threshold
+    int32_t nbb;      // buckets of the backed-off band
     size_t par, occ, keys, sites, counts, prefix, total;
 };
 
@@ -211,19 +214,22 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
     int shift = 64 + bucket_log2 - lgN - p.shift_adj;
     shift = std::max(1, std::min(63, shift));
     s.shift = shift;
-    const unsigned __int128 span_full = (static_cast<unsigned __int128>(1) << 64) - s.T0;
-    unsigned __int128 span;
-    if (p.band_hi >= N) {
-        span = span_full;
-        s.full = 1;
-    } else {
-        const uint64_t Thi = rank_to_key(std::max<int64_t>(p.band_hi, p.n0 + 1), N);
-        span = Thi > s.T0 ? Thi - s.T0 : 1;
-        s.full = 0;
-    }
-    const unsigned __int128 w = static_cast<unsigned __int128>(1) << shift;
-    const unsigned __int128 nb = (span + w - 1) / w;
-    s.nb = static_cast<int32_t>(std::max<unsigned __int128>(1, nb));
+    s.full = p.band_hi >= N ? 1 : 0;
+    const uint64_t Thi = s.full ? 0 : rank_to_key(std::max<int64_t>(p.band_hi, p.n0 + 1), N);
+    // buckets of width 2^shift covering [T, Thi) (or [T, 2^64) for a full band)
+    auto buckets = [&](uint64_t T) {
+        const unsigned __int128 top = s.full ? (static_cast<unsigned __int128>(1) << 64) : Thi;
+        const unsigned __int128 span = top > T ? top - T : 1;
+        const unsigned __int128 w = static_cast<unsigned __int128>(1) << shift;
+        return static_cast<int32_t>(std::max<unsigned __int128>(1, (span + w - 1) / w));
+    };
+    s.nb = buckets(s.T0);
+    // a first backoff is resolved inside the chunk, so the band region is sized
+    // for the backed-off band as well
+    s.n0b = (p.n0 > 0 && p.backoff > 0 && p.n0 - p.backoff > 0) ? p.n0 - p.backoff : 0;
+    s.T0b = s.n0b > 0 ? rank_to_key(s.n0b, N) : 0;
+    s.nbb = s.n0b > 0 ? buckets(s.T0b) : 0;
+    const int32_t nb_alloc = std::max(s.nb, s.nbb);
     const double mean = std::ldexp(static_cast<double>(N), shift - 64);
     int cap = static_cast<int>(std::ceil(mean + 8.0 * std::sqrt(mean) + 16.0));
     cap = (cap + 15) / 16 * 16;
@@ -240,9 +246,9 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
     }
     s.par = align_up(static_cast<size_t>(N) * 4);
     s.occ = align_up(static_cast<size_t>((N + 63) / 64) * 8);
-    s.keys = align_up(static_cast<size_t>(s.nb) * s.cap * 8);
-    s.sites = align_up(static_cast<size_t>(s.nb) * s.cap * 4);
-    s.counts = align_up(static_cast<size_t>(s.nb) * 4);
+    s.keys = align_up(static_cast<size_t>(nb_alloc) * s.cap * 8);
+    s.sites = align_up(static_cast<size_t>(nb_alloc) * s.cap * 4);
+    s.counts = align_up(static_cast<size_t>(nb_alloc) * 4);
     s.prefix = align_up(static_cast<size_t>(s.prefix_cap) * 4);
     s.total = s.par + s.occ + s.keys + s.sites + s.counts + s.prefix;
     return s;
@@ -498,11 +504,11 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 if (events->ok) pe = events;
             }
             if (pe) HIP_TRY(hipEventRecord(pe->ev[0], st));
-            HIP_TRY(nz::launch_clear(d_desc, n, ws, d_state, st));
+            HIP_TRY(nz::launch_clear(d_desc, nullptr, n, ws, d_state, st));
             for (int32_t a = 0; a < n;) {
                 int32_t b = a;
                 while (b < n && desc[b].N == desc[a].N) ++b;
-                HIP_TRY(nz::launch_keys(d_desc, a, b - a, desc[a].N, ws, d_state, st));
+                HIP_TRY(nz::launch_keys(d_desc, nullptr, a, b - a, desc[a].N, ws, d_state, st));
                 a = b;
             }
             if (pe) HIP_TRY(hipEventRecord(pe->ev[1], st));
@@ -511,6 +517,42 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 const int32_t bx_site = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(1024, (max_site + 1023) / 1024)));
                 HIP_TRY(nz::launch_prefill(d_desc, d_list, static_cast<int32_t>(prefill_list.size()), bx_hook, bx_site, d_tabs, ws,
                                            d_state, st));
+                // Resolve first backoffs inside the chunk: samples whose bulk state
+                // already spans are re-keyed and re-labelled from n0 - backoff now,
+                // so they join this chunk's sweep instead of a later redo round.
+                std::vector<NzState> st0(n);
+                HIP_TRY(hipMemcpyAsync(st0.data(), d_state, n * sizeof(NzState), hipMemcpyDeviceToHost, st));
+                HIP_TRY(hipStreamSynchronize(st));
+                std::vector<int32_t> again;
+                for (int32_t di : prefill_list) {
+                    if (st0[di].status != NZ_ST_BACKOFF) continue;
+                    const int32_t ci = chunk_of_desc[di];
+                    const Sizes &s = sizes[ci];
+                    if (s.n0b <= 0) continue;   // no first backoff planned: the redo round takes it
+                    Plan &p = chunk[ci];
+                    ++g_stats[3];
+                    if (h_backoffs) ++h_backoffs[p.job];
+                    p.n0 = s.n0b;
+                    p.backoff = 0;
+                    desc[di].T0 = s.T0b;
+                    desc[di].nb = s.nbb;
+                    max_nb = std::max(max_nb, s.nbb);
+                    again.push_back(di);
+                }
+                if (!again.empty()) {
+                    std::stable_sort(again.begin(), again.end(), [&](int32_t a, int32_t b) { return desc[a].N < desc[b].N; });
+                    const int32_t na = static_cast<int32_t>(again.size());
+                    HIP_TRY(hipMemcpyAsync(d_desc, desc.data(), n * sizeof(NzSample), hipMemcpyHostToDevice, st));
+                    HIP_TRY(hipMemcpyAsync(d_list, again.data(), na * sizeof(int32_t), hipMemcpyHostToDevice, st));
+                    HIP_TRY(nz::launch_clear(d_desc, d_list, na, ws, d_state, st));
+                    for (int32_t a = 0; a < na;) {
+                        int32_t b = a;
+                        while (b < na && desc[again[b]].N == desc[again[a]].N) ++b;
+                        HIP_TRY(nz::launch_keys(d_desc, d_list, a, b - a, desc[again[a]].N, ws, d_state, st));
+                        a = b;
+                    }
+                    HIP_TRY(nz::launch_prefill(d_desc, d_list, na, bx_hook, bx_site, d_tabs, ws, d_state, st));
+                }
             }
             if (pe) HIP_TRY(hipEventRecord(pe->ev[2], st));
             HIP_TRY(nz::launch_sort(d_desc, n, max_nb, max_cap, ws, st));

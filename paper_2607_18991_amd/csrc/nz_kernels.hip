@@ -9,8 +9,8 @@
 //                      sites in the key band [T0, T0 + nb << shift) are appended
 //                      to the bucket of their key;
 //   nz_hook/compress/  bulk connected components of the prefilled sites
-//   rootmark/accum/    (hook-and-compress with CAS links, then cluster sizes and
-//   span kernels       border flags into the root word); a state that already
+//   accum kernels      (hook-and-compress with CAS links, then cluster sizes and
+//                      border flags into the root word); a state that already
 //                      spans is flagged for backoff;
 //   nz_sort_kernel     each bucket sorted by (key, site) in LDS (bitonic);
 //                      concatenated buckets are exactly the occupation order;
@@ -108,11 +108,11 @@ __device__ __forceinline__ T bcast(T v, int lane)
 // ---------------------------------------------------------------------------
 // Clearing: bucket counters and per-sample state of a chunk.
 
-__global__ __launch_bounds__(256) void nz_clear_kernel(const NzSample *__restrict__ desc, int32_t nsamp,
-                                                       uint8_t *__restrict__ ws, NzState *__restrict__ state)
+__global__ __launch_bounds__(256) void nz_clear_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
+                                                       int32_t nsamp, uint8_t *__restrict__ ws, NzState *__restrict__ state)
 {
-    const int sid = blockIdx.x;
-    if (sid >= nsamp) return;
+    if (static_cast<int32_t>(blockIdx.x) >= nsamp) return;
+    const int sid = list ? list[blockIdx.x] : static_cast<int>(blockIdx.x);
     const NzSample &d = desc[sid];
     uint32_t *counts = reinterpret_cast<uint32_t *>(ws + d.off_counts);
     for (int b = threadIdx.x; b < d.nb; b += blockDim.x) counts[b] = 0u;
@@ -135,11 +135,17 @@ constexpr int KEYS_THREADS = 256;
 constexpr int KEYS_ITERS = 16;
 constexpr int KEYS_SITES_PER_BLOCK = KEYS_THREADS * KEYS_ITERS;
 
-__global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *__restrict__ desc, int32_t first,
+__global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *__restrict__ desc,
+                                                               const int32_t *__restrict__ list, int32_t first,
                                                                int32_t blocks_per_sample, uint8_t *__restrict__ ws,
                                                                NzState *__restrict__ state)
 {
-    const int sid = first + static_cast<int>(blockIdx.x) / blocks_per_sample;
+    // prefilled sites of this block, staged in LDS and appended to the
+    // sample's list with one global atomic per block
+    __shared__ uint32_t pre_sites[KEYS_SITES_PER_BLOCK];
+    __shared__ uint32_t pre_count, pre_base;
+    const int which = static_cast<int>(blockIdx.x) / blocks_per_sample;
+    const int sid = list ? list[first + which] : first + which;
     const int blk = static_cast<int>(blockIdx.x) % blocks_per_sample;
     const NzSample &d = desc[sid];
     const uint32_t N = static_cast<uint32_t>(d.N);
@@ -161,6 +167,8 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
 
     const uint32_t lane = lane_id();
     const uint32_t block_base = static_cast<uint32_t>(blk) * KEYS_SITES_PER_BLOCK;
+    if (threadIdx.x == 0) pre_count = 0u;
+    __syncthreads();
     for (int it = 0; it < KEYS_ITERS; ++it) {
         const uint32_t wbase = block_base + it * KEYS_THREADS + (threadIdx.x & ~63u);
         if (wbase >= N) break;
@@ -176,10 +184,7 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
         occ[(wbase >> 5) + (lane & 1u)] = static_cast<uint32_t>(bal >> (32u * (lane & 1u)));
         if (pre) {
             par[i] = static_cast<int32_t>(i);
-            // per-lane append; the compiler's atomic optimiser folds the wave's
-            // appends into one atomic
-            const uint32_t pos = atomicAdd(reinterpret_cast<uint32_t *>(&state[sid].n0), 1u);
-            if (pos < static_cast<uint32_t>(d.prefix_cap)) prefix[pos] = i;
+            pre_sites[atomicAdd(&pre_count, 1u)] = i;
         }
         if (valid && !pre) {
             const uint64_t b = (K - T0) >> shift;
@@ -190,6 +195,17 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
                     sites[b * cap + slot] = pack_coords(i, L, magic);
                 }
             }
+        }
+    }
+    __syncthreads();
+    const uint32_t cnt = pre_count;
+    if (cnt) {
+        if (threadIdx.x == 0) pre_base = atomicAdd(reinterpret_cast<uint32_t *>(&state[sid].n0), cnt);
+        __syncthreads();
+        const uint32_t base = pre_base;
+        for (uint32_t k = threadIdx.x; k < cnt; k += KEYS_THREADS) {
+            const uint32_t pos = base + k;
+            if (pos < static_cast<uint32_t>(d.prefix_cap)) prefix[pos] = pre_sites[k];
         }
     }
 }
@@ -319,6 +335,18 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
     }
 }
 
+__device__ __forceinline__ uint32_t border_flags(uint32_t s, uint32_t L, uint64_t magic)
+{
+    const uint32_t x0 = s - div_by_L(s, magic) * L;
+    return (x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u);
+}
+
+// Compress: every member points straight at its root, and every root takes its
+// root word (size 1 plus its own border flags).  Each thread writes only its
+// own entry and walks the forest read-only: a halving write here could replace
+// an entry another thread has already pointed at its root with a non-root
+// ancestor.  Roots never change in this kernel, so a walk stops at an entry that
+// points to itself or already holds a root word.
 __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
                                                           uint8_t *__restrict__ ws, NzState *__restrict__ state)
 {
@@ -326,69 +354,33 @@ __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__rest
     const NzSample &d = desc[sid];
     const int32_t n0 = state[sid].n0;
     if (n0 > d.prefix_cap) return;
+    const uint32_t L = static_cast<uint32_t>(d.L);
     int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
-    // Each thread writes only its own entry and walks the forest read-only: a
-    // halving write here could replace an entry that another thread has
-    // already pointed at its root with a non-root ancestor, and the size pass
-    // below relies on every member pointing straight at its root.  Roots do
-    // not change during this kernel, so every walk ends at the final root.
     for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n0; k += gridDim.x * blockDim.x) {
         const int32_t s = static_cast<int32_t>(prefix[k]);
         int32_t r = s;
         int32_t p = ld_a(&par[r]);
-        while (p != r) {
+        while (p >= 0 && p != r) {
             r = p;
             p = ld_a(&par[r]);
         }
-        st_a(&par[s], r);
-    }
-}
-
-__global__ __launch_bounds__(256) void nz_rootmark_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
-                                                          uint8_t *__restrict__ ws, NzState *__restrict__ state)
-{
-    const int sid = list[blockIdx.y];
-    const NzSample &d = desc[sid];
-    const int32_t n0 = state[sid].n0;
-    if (n0 > d.prefix_cap) return;
-    const uint32_t L = static_cast<uint32_t>(d.L);
-    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
-    const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
-    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n0; k += gridDim.x * blockDim.x) {
-        const int32_t s = static_cast<int32_t>(prefix[k]);
-        if (par[s] == s) {
-            const uint32_t x0 = static_cast<uint32_t>(s) - div_by_L(static_cast<uint32_t>(s), d.magic) * L;
-            const uint32_t fl = (x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u);
-            par[s] = static_cast<int32_t>(NZ_ROOT | fl | 1u);
+        if (r == s) {
+            const uint32_t fl = border_flags(static_cast<uint32_t>(s), L, d.magic);
+            st_a(&par[s], static_cast<int32_t>(NZ_ROOT | fl | 1u));
+            if (fl == NZ_FLAGS) state[sid].status = NZ_ST_BACKOFF;   // L = 1: one site spans
+        } else {
+            st_a(&par[s], r);
         }
     }
 }
 
+// Sizes and border flags of the prefilled clusters: members add themselves to
+// their root word.  The flag OR returns the previous word, so the member that
+// completes a root's pair of border flags sees it: the state already spans and
+// the sample backs off.
 __global__ __launch_bounds__(256) void nz_accum_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
                                                        uint8_t *__restrict__ ws, NzState *__restrict__ state)
-{
-    const int sid = list[blockIdx.y];
-    const NzSample &d = desc[sid];
-    const int32_t n0 = state[sid].n0;
-    if (n0 > d.prefix_cap) return;
-    const uint32_t L = static_cast<uint32_t>(d.L);
-    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
-    const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
-    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n0; k += gridDim.x * blockDim.x) {
-        const int32_t s = static_cast<int32_t>(prefix[k]);
-        const int32_t r = par[s];
-        if (r >= 0) {
-            const uint32_t x0 = static_cast<uint32_t>(s) - div_by_L(static_cast<uint32_t>(s), d.magic) * L;
-            const uint32_t fl = (x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u);
-            atomicAdd(reinterpret_cast<uint32_t *>(&par[r]), 1u);
-            if (fl) atomicOr(reinterpret_cast<uint32_t *>(&par[r]), fl);
-        }
-    }
-}
-
-__global__ __launch_bounds__(256) void nz_span_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
-                                                      uint8_t *__restrict__ ws, NzState *__restrict__ state)
 {
     const int sid = list[blockIdx.y];
     const NzSample &d = desc[sid];
@@ -397,11 +389,21 @@ __global__ __launch_bounds__(256) void nz_span_kernel(const NzSample *__restrict
         if (blockIdx.x == 0 && threadIdx.x == 0) state[sid].status = NZ_ST_PREFIX;
         return;
     }
-    const int32_t *par = reinterpret_cast<const int32_t *>(ws + d.off_par);
+    const uint32_t L = static_cast<uint32_t>(d.L);
+    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
     for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n0; k += gridDim.x * blockDim.x) {
-        const uint32_t v = static_cast<uint32_t>(par[prefix[k]]);
-        if ((v & NZ_ROOT) && (v & NZ_FLAGS) == NZ_FLAGS) state[sid].status = NZ_ST_BACKOFF;
+        const int32_t s = static_cast<int32_t>(prefix[k]);
+        const int32_t r = par[s];
+        if (r >= 0) {
+            uint32_t *root = reinterpret_cast<uint32_t *>(&par[r]);
+            atomicAdd(root, 1u);
+            const uint32_t fl = border_flags(static_cast<uint32_t>(s), L, d.magic);
+            if (fl) {
+                const uint32_t old = atomicOr(root, fl);
+                if (((old | fl) & NZ_FLAGS) == NZ_FLAGS) state[sid].status = NZ_ST_BACKOFF;
+            }
+        }
     }
 }
 
@@ -671,22 +673,23 @@ __global__ void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
 
 namespace nz {
 
-hipError_t launch_clear(const NzSample *desc, int32_t nsamp, uint8_t *ws, NzState *state, hipStream_t st)
+hipError_t launch_clear(const NzSample *desc, const int32_t *list, int32_t nsamp, uint8_t *ws, NzState *state,
+                        hipStream_t st)
 {
     if (nsamp <= 0) return hipSuccess;
-    hipLaunchKernelGGL(nz_clear_kernel, dim3(nsamp), dim3(256), 0, st, desc, nsamp, ws, state);
+    hipLaunchKernelGGL(nz_clear_kernel, dim3(nsamp), dim3(256), 0, st, desc, list, nsamp, ws, state);
     return hipGetLastError();
 }
 
-hipError_t launch_keys(const NzSample *desc, int32_t first, int32_t count, int32_t N, uint8_t *ws, NzState *state,
-                       hipStream_t st)
+hipError_t launch_keys(const NzSample *desc, const int32_t *list, int32_t first, int32_t count, int32_t N, uint8_t *ws,
+                       NzState *state, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
     const int32_t bps = (N + KEYS_SITES_PER_BLOCK - 1) / KEYS_SITES_PER_BLOCK;
     const int64_t blocks = static_cast<int64_t>(bps) * count;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(nz_keys_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(KEYS_THREADS), 0, st, desc, first, bps,
-                       ws, state);
+    hipLaunchKernelGGL(nz_keys_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(KEYS_THREADS), 0, st, desc, list, first,
+                       bps, ws, state);
     return hipGetLastError();
 }
 
@@ -711,9 +714,7 @@ hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nli
     if (nlist <= 0) return hipSuccess;
     hipLaunchKernelGGL(nz_hook_kernel, dim3(bx_hook, nlist), dim3(256), 0, st, desc, list, tabs, ws, state);
     hipLaunchKernelGGL(nz_compress_kernel, dim3(bx_site, nlist), dim3(256), 0, st, desc, list, ws, state);
-    hipLaunchKernelGGL(nz_rootmark_kernel, dim3(bx_site, nlist), dim3(256), 0, st, desc, list, ws, state);
     hipLaunchKernelGGL(nz_accum_kernel, dim3(bx_site, nlist), dim3(256), 0, st, desc, list, ws, state);
-    hipLaunchKernelGGL(nz_span_kernel, dim3(bx_site, nlist), dim3(256), 0, st, desc, list, ws, state);
     return hipGetLastError();
 }
 

@@ -6,12 +6,15 @@
 
 namespace nz {
 
-hipError_t launch_clear(const NzSample *desc, int32_t nsamp, uint8_t *ws, NzState *state, hipStream_t st);
+// Samples 0..nsamp-1, or list[0..nsamp) when list != NULL.
+hipError_t launch_clear(const NzSample *desc, const int32_t *list, int32_t nsamp, uint8_t *ws, NzState *state,
+                        hipStream_t st);
 
 // Keys for samples [first, first + count) of the descriptor array, all of
 // lattice size N.
-hipError_t launch_keys(const NzSample *desc, int32_t first, int32_t count, int32_t N, uint8_t *ws, NzState *state,
-                       hipStream_t st);
+// (list != NULL: samples list[first .. first + count) instead).
+hipError_t launch_keys(const NzSample *desc, const int32_t *list, int32_t first, int32_t count, int32_t N, uint8_t *ws,
+                       NzState *state, hipStream_t st);
 int32_t keys_sites_per_block();
 
 hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int32_t max_cap, uint8_t *ws,

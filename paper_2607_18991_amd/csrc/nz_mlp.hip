@@ -1,5 +1,6 @@
 // nz_mlp.hip -- the small MLP of the learned prefill: (7 zone-mask bits,
-// standardised ln L) -> 64 -> 64 -> (u, v), tanh after the hidden layers; u, v
+// standardised size variable L^(-1/nu)) -> 64 -> 64 -> (u, v), tanh after the
+// hidden layers; u, v
 // estimate ln mean and ln std of n*/N.  Weights are stored as bfloat16 and
 // widened exactly to float; every product and sum is FP32.  The network is
 // about 5k parameters and is evaluated for a few hundred rows, so the kernels

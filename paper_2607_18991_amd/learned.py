@@ -47,28 +47,42 @@ def init_params(seed: int = 0) -> np.ndarray:
     return flat
 
 
+# The size input: ln L enters through the finite-size-scaling variable
+# exp(-ln L / nu) = L^(-1/nu), nu_5 = 0.5720 (the 5D correlation-length exponent
+# quoted in Sec. II.A.3).  The mean of n*/N approaches p_c roughly linearly in it,
+# so lattices larger than the training ones sit just beyond the training range
+# where the curves flatten, instead of far out on a ln L axis.
+NU5 = 0.5720
+
+
+def size_variable(L: int) -> float:
+    return math.exp(-math.log(L) / NU5)
+
+
 class PrefillModel:
-    def __init__(self, params: np.ndarray, lnL_mean: float, lnL_std: float, meta: dict | None = None):
+    def __init__(self, params: np.ndarray, size_mean: float, size_std: float, meta: dict | None = None):
         self.params = np.asarray(params, dtype=np.float32)
-        self.lnL_mean = float(lnL_mean)
-        self.lnL_std = float(lnL_std)
+        self.size_mean = float(size_mean)
+        self.size_std = float(size_std)
         self.meta = meta or {}
 
     # ---------------------------------------------------------------- io
     def save(self, path: str = DEFAULT_PATH) -> None:
         with open(path, "w") as f:
-            json.dump({"lnL_mean": self.lnL_mean, "lnL_std": self.lnL_std, "meta": self.meta,
+            json.dump({"size_feature": "L^(-1/nu)", "nu": NU5, "size_mean": self.size_mean,
+                       "size_std": self.size_std, "meta": self.meta,
                        "params_fp32": [float(v) for v in self.params]}, f)
 
     @classmethod
     def load(cls, path: str = DEFAULT_PATH) -> "PrefillModel":
         with open(path) as f:
             d = json.load(f)
-        return cls(np.array(d["params_fp32"], dtype=np.float32), d["lnL_mean"], d["lnL_std"], d.get("meta"))
+        return cls(np.array(d["params_fp32"], dtype=np.float32), d["size_mean"], d["size_std"], d.get("meta"))
 
     # ---------------------------------------------------------------- inference
     def features(self, masks, Ls) -> np.ndarray:
-        rows = [zone_bits(int(m)) + [(math.log(int(L)) - self.lnL_mean) / self.lnL_std] for m, L in zip(masks, Ls)]
+        rows = [zone_bits(int(m)) + [(size_variable(int(L)) - self.size_mean) / self.size_std]
+                for m, L in zip(masks, Ls)]
         return np.array(rows, dtype=np.float32).reshape(-1, IN)
 
     def predict(self, masks, Ls, stream=None):
@@ -127,11 +141,11 @@ def train(points, steps: int = 3000, lr: float = 3e-3, seed: int = 0, log_every:
     import torch
 
     Ls = np.array([p["L"] for p in points], dtype=np.float64)
-    lnL = np.log(Ls)
+    sv = np.array([size_variable(int(L)) for L in Ls])
     w = np.array([p["count"] for p in points], dtype=np.float64)
-    lnL_mean = float(lnL.mean())
-    lnL_std = float(lnL.std()) if lnL.std() > 0 else 1.0
-    model = PrefillModel(init_params(seed), lnL_mean, lnL_std)
+    s_mean = float(sv.mean())
+    s_std = float(sv.std()) if sv.std() > 0 else 1.0
+    model = PrefillModel(init_params(seed), s_mean, s_std)
     x = torch.from_numpy(model.features([p["mask"] for p in points], [p["L"] for p in points])).cuda()
     tgt = torch.from_numpy(np.array([[math.log(p["mean"]), math.log(p["std"])] for p in points],
                                     dtype=np.float32)).cuda()
