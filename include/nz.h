@@ -121,12 +121,17 @@ typedef struct {
  *   wg_waves        waves per workgroup of the sweep (1..16).
  *   waves_per_simd  resident sweep waves per SIMD of the persistent launch.
  *   bucket_log2     log2 of the mean number of keys per sort bucket (4..10).
+ *   sweep_mode      1: one site per wave step (z lanes check the neighbours);
+ *                   2: 64 sites per wave step (one site per lane, unions
+ *                   replayed in order on a register union-find; a block that
+ *                   does not fit it is redone one site at a time).
  */
 typedef struct {
     int32_t residency;
     int32_t wg_waves;
     int32_t waves_per_simd;
     int32_t bucket_log2;
+    int32_t sweep_mode;
 } nz_tuning;
 
 /* Device workspace bytes that lets nz_sweep_batch run the jobs with all their

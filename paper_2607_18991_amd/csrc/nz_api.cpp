@@ -277,6 +277,7 @@ struct Tune {
     int waves_per_simd = 0;
     int bucket_log2 = 8;
     int dcap = 64;
+    int sweep_mode = 0;
 };
 
 int check_job(const nz_job &j, int idx)
@@ -303,6 +304,8 @@ int read_tune(const nz_tuning *t, Tune &out)
         return fail(NZ_EINVAL, "tuning: waves_per_simd %d outside [0, 8]", t->waves_per_simd);
     if (t->bucket_log2 != 0 && (t->bucket_log2 < 4 || t->bucket_log2 > 10))
         return fail(NZ_EINVAL, "tuning: bucket_log2 %d outside [4, 10]", t->bucket_log2);
+    if (t->sweep_mode < 0 || t->sweep_mode > 2) return fail(NZ_EINVAL, "tuning: sweep_mode %d outside [0, 2]", t->sweep_mode);
+    out.sweep_mode = t->sweep_mode;
     out.residency = t->residency;
     out.wg_waves = t->wg_waves;
     out.waves_per_simd = t->waves_per_simd;
@@ -317,6 +320,16 @@ int nch_for(int z)
     if (z <= 256) return 4;
     if (z <= 512) return 8;
     return 14;
+}
+
+// Debug override of the earlier roots one block may touch (tests force the
+// block sweep's one-site-at-a-time fallback).
+int env_blk_old()
+{
+    const char *e = getenv("NZ_DEBUG_BLOCK_OLD");
+    if (!e) return 256;
+    int v = atoi(e);
+    return std::max(0, std::min(256, v));
 }
 
 // Debug override of the distinct-root list size (tests force early merges).
@@ -561,14 +574,16 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             int residency = tune.residency == 3 ? 2 : (tune.residency == 1 ? 1 : 0);
             const uint32_t occ_words = ((max_N + 63) / 64) * 2;
             uint32_t lds_words = residency == 2 ? occ_words + max_N : (residency == 1 ? occ_words : 0);
+            const bool block = tune.sweep_mode != 1;
+            if (block) lds_words += nz::block_lds_words();
             int wg_waves = tune.wg_waves ? tune.wg_waves : (residency ? 1 : 4);
             int wps = tune.waves_per_simd ? tune.waves_per_simd : 8;
             size_t lds_wg = static_cast<size_t>(lds_words) * 4 * wg_waves;
-            if (residency && lds_wg > dev.lds_per_block)
+            if (lds_wg > dev.lds_per_block)
                 return fail(NZ_EUNSUPPORTED, "residency %d needs %zu bytes of LDS per workgroup; the device allows %zu",
                             tune.residency, lds_wg, dev.lds_per_block);
             int wgs_per_cu = std::max(1, 4 * wps / wg_waves);
-            if (residency && lds_wg > 0) wgs_per_cu = std::max<int>(1, std::min<size_t>(wgs_per_cu, dev.lds_per_cu / lds_wg));
+            if (lds_wg > 0) wgs_per_cu = std::max<int>(1, std::min<size_t>(wgs_per_cu, dev.lds_per_cu / lds_wg));
             int grid = dev.cus * wgs_per_cu;
             grid = std::min(grid, (n + wg_waves - 1) / wg_waves);
             NzSweepArgs args;
@@ -581,7 +596,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             args.state = d_state;
             args.lds_words = lds_words;
             args.dcap = tune.dcap;
-            HIP_TRY(nz::launch_sweep(nch_for(max_z), residency, args, d_nstar, d_mass, d_outidx, grid, wg_waves, st));
+            args.blk_old = env_blk_old();
+            HIP_TRY(nz::launch_sweep(nch_for(max_z), residency, block, args, d_nstar, d_mass, d_outidx, grid, wg_waves, st));
             if (pe) HIP_TRY(hipEventRecord(pe->ev[4], st));
 
             // ---- read back and schedule the redo of unfinished samples

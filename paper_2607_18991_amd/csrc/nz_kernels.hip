@@ -433,6 +433,21 @@ struct SweepMem {
         if constexpr (RES == RES_HBM) st_w(&occ_g[w], v);
         else st_w(&lds[lbase + w], v);
     }
+    // several lanes may set bits of one word at once
+    __device__ __forceinline__ void occ_or(uint32_t *lds, uint32_t w, uint32_t bits) const
+    {
+        if constexpr (RES == RES_HBM)
+            __hip_atomic_fetch_or(&occ_g[w], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        else
+            __hip_atomic_fetch_or(&lds[lbase + w], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
+    __device__ __forceinline__ void occ_andn(uint32_t *lds, uint32_t w, uint32_t bits) const
+    {
+        if constexpr (RES == RES_HBM)
+            __hip_atomic_fetch_and(&occ_g[w], ~bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        else
+            __hip_atomic_fetch_and(&lds[lbase + w], ~bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+    }
     __device__ __forceinline__ int32_t par_ld(uint32_t *lds, int32_t i) const
     {
         if constexpr (RES == RES_ALL) return static_cast<int32_t>(ld_w(&lds[lbase + occ_words + i]));
@@ -445,11 +460,12 @@ struct SweepMem {
     }
 };
 
-// Root of x with path halving; returns the root index and its root word.
+// Root of x with path halving, given v = the parent word of x; returns the root
+// index and its root word.
 template <int RES>
-__device__ __forceinline__ void sweep_find(const SweepMem<RES> &m, uint32_t *lds, int32_t x, int32_t &root, uint32_t &word)
+__device__ __forceinline__ void sweep_find_from(const SweepMem<RES> &m, uint32_t *lds, int32_t x, int32_t v,
+                                                int32_t &root, uint32_t &word)
 {
-    int32_t v = m.par_ld(lds, x);
     while (v >= 0) {
         const int32_t g = m.par_ld(lds, v);
         if (g < 0) {
@@ -463,6 +479,12 @@ __device__ __forceinline__ void sweep_find(const SweepMem<RES> &m, uint32_t *lds
     }
     root = x;
     word = static_cast<uint32_t>(v);
+}
+
+template <int RES>
+__device__ __forceinline__ void sweep_find(const SweepMem<RES> &m, uint32_t *lds, int32_t x, int32_t &root, uint32_t &word)
+{
+    sweep_find_from<RES>(m, lds, x, m.par_ld(lds, x), root, word);
 }
 
 // Merge the D distinct roots held by lanes 0..D-1 (lroot/lword) into the largest
@@ -494,13 +516,410 @@ __device__ __forceinline__ int32_t sweep_merge(const SweepMem<RES> &m, uint32_t 
     return best;
 }
 
+// The key band of one sample in (key, site) order: buckets in key order, each
+// already sorted; 64 entries are fetched at a time into one register per lane.
+struct BandCursor {
+    const uint32_t *counts;
+    const uint32_t *sites;
+    uint32_t cap;
+    int32_t nb;
+    int32_t b;        // current bucket
+    uint32_t cnt;     // entries in it
+    uint32_t j;       // next entry
+    uint32_t base;    // entry held by lane 0
+    uint32_t mine;    // entry base + lane
+
+    __device__ __forceinline__ void init(const uint32_t *c, const uint32_t *s, uint32_t cp, int32_t n)
+    {
+        counts = c;
+        sites = s;
+        cap = cp;
+        nb = n;
+        b = -1;
+        cnt = 0;
+        j = 0;
+        base = 0;
+        mine = 0;
+    }
+
+    // 1: pc holds the next site; 0: the band is exhausted; -1: the next
+    // non-empty bucket overflowed its capacity.
+    __device__ __forceinline__ int next(uint32_t &pc, uint32_t lane)
+    {
+        while (j >= cnt) {
+            ++b;
+            if (b >= nb) return 0;
+            cnt = counts[b];
+            if (cnt > cap) return -1;
+            j = 0;
+            base = 0;
+            mine = lane < cnt ? sites[static_cast<uint64_t>(b) * cap + lane] : 0u;
+        }
+        if (j - base >= 64u) {
+            base = j;
+            mine = base + lane < cnt ? sites[static_cast<uint64_t>(b) * cap + base + lane] : 0u;
+        }
+        pc = bcast(mine, static_cast<int>(j - base));
+        ++j;
+        return 1;
+    }
+};
+
+// One sequential step's site and the occupancy words of its neighbours (lane
+// c*64 + lane holds neighbour c of the offset table).
+template <int NCH>
+struct SiteStep {
+    int32_t s;
+    uint32_t fl;
+    uint32_t own;
+    uint32_t word[NCH];
+    int32_t tn[NCH];
+    bool inb[NCH];
+
+    template <int RES>
+    __device__ __forceinline__ void prepare(const SweepMem<RES> &m, uint32_t *lds, uint32_t pc, int32_t L,
+                                            const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH])
+    {
+        const int32_t x0 = pc & 63, x1 = (pc >> 6) & 63, x2 = (pc >> 12) & 63, x3 = (pc >> 18) & 63, x4 = pc >> 24;
+        s = x0 + L * (x1 + L * (x2 + L * (x3 + L * x4)));
+        const uint32_t A = allowed_axis(x0, L) | (allowed_axis(x1, L) << 5) | (allowed_axis(x2, L) << 10) |
+                           (allowed_axis(x3, L) << 15) | (allowed_axis(x4, L) << 20);
+        fl = (x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u);
+        own = m.occ_ld(lds, static_cast<uint32_t>(s) >> 5);
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            inb[c] = (ocode[c] & ~A) == 0u;
+            tn[c] = s + ostride[c];
+            word[c] = inb[c] ? m.occ_ld(lds, static_cast<uint32_t>(tn[c]) >> 5) : 0u;
+        }
+    }
+
+    // Account for site p, occupied after these words were loaded.
+    __device__ __forceinline__ void patch(int32_t p)
+    {
+        const uint32_t bit = 1u << (p & 31);
+        if ((s >> 5) == (p >> 5)) own |= bit;
+#pragma unroll
+        for (int c = 0; c < NCH; ++c)
+            if (inb[c] && tn[c] == p) word[c] |= bit;
+    }
+};
+
+// The next site's occupancy is loaded one step ahead only while the doubled
+// per-lane arrays stay small (z <= 128); wider neighbourhoods have few
+// sequential steps and would spill registers.
+template <int NCH>
+constexpr bool kLookahead = NCH <= 2;
+
+// One sequential addition: store the site's occupancy bit, find the distinct
+// roots of its occupied neighbours (lanes 0..D-1 hold them, entry 0 being the
+// site itself), and merge them into the largest.  Returns the merged cluster's
+// size and border flags.
+template <int NCH, int RES>
+__device__ __forceinline__ void sweep_step(const SweepMem<RES> &m, uint32_t *lds, const SiteStep<NCH> &cur, int dcap,
+                                           uint32_t &total, uint32_t &flags)
+{
+    const uint32_t lane = lane_id();
+    const int32_t s = cur.s;
+    // all lanes store the same updated word of s (this wave is the only writer
+    // of the sample's bitset)
+    m.occ_st(lds, static_cast<uint32_t>(s) >> 5, cur.own | (1u << (s & 31)));
+
+    int32_t lroot = s;
+    uint32_t lword = NZ_ROOT | cur.fl | 1u;
+    int D = 1;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const bool o = cur.inb[c] && ((cur.word[c] >> (cur.tn[c] & 31)) & 1u);
+        uint64_t mk = __ballot(o);
+        if (!mk) continue;
+        int32_t root = 0;
+        uint32_t rw = 0;
+        if (o) sweep_find<RES>(m, lds, cur.tn[c], root, rw);
+        bool stale = false;   // a flush since these finds may have linked their roots
+        while (mk) {
+            const int l = __builtin_ctzll(mk);
+            mk &= mk - 1;
+            int32_t rr = bcast(root, l);
+            uint32_t rrw = bcast(rw, l);
+            if (stale) sweep_find<RES>(m, lds, rr, rr, rrw);
+            if (__ballot(static_cast<int>(lane) < D && lroot == rr)) continue;
+            if (D == dcap) {
+                // list full: merge what we have and keep only the survivor;
+                // rr is not in the list, so the flush leaves it a root
+                uint32_t tot, flg;
+                const int32_t w = sweep_merge<RES>(m, lds, D, lroot, lword, tot, flg);
+                lroot = lane == 0 ? w : lroot;
+                lword = lane == 0 ? (NZ_ROOT | flg | tot) : lword;
+                D = 1;
+                stale = true;
+            }
+            lroot = static_cast<int>(lane) == D ? rr : lroot;
+            lword = static_cast<int>(lane) == D ? rrw : lword;
+            ++D;
+        }
+    }
+    sweep_merge<RES>(m, lds, D, lroot, lword, total, flags);
+}
+
+// ---------------------------------------------------------------------------
+// Block sweep: the next 64 sites of the order are added by one wave at once,
+// one site per lane.  The neighbour checks and root finds of the 64 sites
+// overlap in memory instead of following each other; the unions run as a small
+// connected-components pass over a graph whose nodes are the block's sites and
+// the earlier clusters they touch.  Spanning is monotone in the occupation (a
+// cluster only grows and its border flags only accumulate), so if no cluster
+// spans after all 64 additions none spanned after any of them and the block is
+// committed as a whole.  The single block in which the first spanning cluster
+// appears, and blocks that do not fit the tables below, are undone and redone
+// one site at a time, which yields the exact n* and mass.
+//
+// Per-wave LDS slice (32-bit words, at the end of the wave's slice):
+//   bkey[256] bpos[256]  open-addressing table: block site -> position
+//   rkey[256]            open-addressing table of the earlier roots touched
+//   npar[320]            node parents: node i < 64 is position i, node 64 + h
+//                        the earlier root in rkey slot h
+//   nword[320]           node words in the root-word format (size, flags)
+
+constexpr int BLK_K = 8;               // occupied earlier neighbours recorded per site
+constexpr uint32_t BLK_BSLOTS = 256;
+constexpr uint32_t BLK_RSLOTS = 256;
+constexpr uint32_t BLK_NODES = 64 + BLK_RSLOTS;
+constexpr uint32_t BLK_EMPTY = 0xFFFFFFFFu;
+constexpr uint32_t BLK_LDS_WORDS = 2 * BLK_BSLOTS + BLK_RSLOTS + 2 * BLK_NODES;
+constexpr int BLK_CHUNK = 16;          // neighbour offsets whose loads are issued together
+
+__device__ __forceinline__ uint32_t blk_hash(uint32_t t) { return (t * 0x9E3779B1u) >> 24; }
+
+// Root of node n in the LDS forest, with path halving.  Only non-roots are
+// rewritten (to an ancestor), and hooks only change roots, so concurrent finds
+// and hooks of the lanes of one wave keep the forest acyclic.
+__device__ __forceinline__ uint32_t blk_find(uint32_t *npar, uint32_t x)
+{
+    for (;;) {
+        const uint32_t p = ld_w(&npar[x]);
+        if (p == x) return x;
+        const uint32_t g = ld_w(&npar[p]);
+        if (g == p) return p;
+        st_w(&npar[x], g);
+        x = g;
+    }
+}
+
+enum { BLK_COMMITTED = 0, BLK_FALLBACK = 1 };
+
+// Adds the nbk (1..64) sites whose packed coordinates lane i holds in pc (lane
+// i = position i of the order).  BLK_COMMITTED: the block is merged into the
+// union-find and no cluster spans.  BLK_FALLBACK: the occupancy bits of the
+// block are cleared again and parents are as before (up to path halving); the
+// caller adds the sites one at a time.
+template <int RES>
+__device__ __forceinline__ int block_step(const SweepMem<RES> &m, uint32_t *lds, uint32_t hbase, int nbk, uint32_t pc,
+                                          int32_t L, const NzOffset *tab, int32_t z, int max_old)
+{
+    const uint32_t lane = lane_id();
+    const bool act = static_cast<int>(lane) < nbk;
+    const int32_t x0 = pc & 63, x1 = (pc >> 6) & 63, x2 = (pc >> 12) & 63, x3 = (pc >> 18) & 63, x4 = pc >> 24;
+    const int32_t s = x0 + L * (x1 + L * (x2 + L * (x3 + L * x4)));
+    const uint32_t A = allowed_axis(x0, L) | (allowed_axis(x1, L) << 5) | (allowed_axis(x2, L) << 10) |
+                       (allowed_axis(x3, L) << 15) | (allowed_axis(x4, L) << 20);
+    const uint32_t fl = (x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u);
+    uint32_t *bkey = lds + hbase;
+    uint32_t *bpos = bkey + BLK_BSLOTS;
+    uint32_t *rkey = bpos + BLK_BSLOTS;
+    uint32_t *npar = rkey + BLK_RSLOTS;
+    uint32_t *nword = npar + BLK_NODES;
+
+    // 1. clear the tables, enter the block's sites, mark them occupied
+#pragma unroll
+    for (uint32_t w = 0; w < BLK_BSLOTS; w += 64) st_w(&bkey[w + lane], BLK_EMPTY);
+#pragma unroll
+    for (uint32_t w = 0; w < BLK_RSLOTS; w += 64) st_w(&rkey[w + lane], BLK_EMPTY);
+    for (uint32_t n = lane; n < BLK_NODES; n += 64) st_w(&npar[n], n);
+    st_w(&nword[lane], act ? (NZ_ROOT | fl | 1u) : 0u);
+    __builtin_amdgcn_wave_barrier();
+    if (act) {
+        uint32_t h = blk_hash(static_cast<uint32_t>(s));
+        for (;;) {   // at most 64 keys in 256 slots: an empty slot is always found
+            uint32_t expected = BLK_EMPTY;
+            if (__hip_atomic_compare_exchange_strong(&bkey[h], &expected, static_cast<uint32_t>(s), __ATOMIC_RELAXED,
+                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)) {
+                st_w(&bpos[h], lane);
+                break;
+            }
+            h = (h + 1) & (BLK_BSLOTS - 1);
+        }
+        m.occ_or(lds, static_cast<uint32_t>(s) >> 5, 1u << (s & 31));
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // 2. occupied neighbours that precede the site: sites of earlier blocks
+    //    (recorded as the site) and earlier positions of this block (recorded
+    //    as -(position + 1)); later positions of the block are skipped
+    int32_t nl[BLK_K];
+#pragma unroll
+    for (int k = 0; k < BLK_K; ++k) nl[k] = 0;
+    int cntn = 0;
+    for (int c0 = 0; c0 < z; c0 += BLK_CHUNK) {
+        int32_t tq[BLK_CHUNK];
+        uint32_t wq[BLK_CHUNK];
+#pragma unroll
+        for (int q = 0; q < BLK_CHUNK; ++q) {
+            NzOffset o;
+            o.stride = 0;
+            o.code = 0xFFFFFFFFu;
+            if (c0 + q < z) o = tab[c0 + q];
+            const bool ok = act && (o.code & ~A) == 0u;
+            tq[q] = s + o.stride;
+            wq[q] = ok ? m.occ_ld(lds, static_cast<uint32_t>(tq[q]) >> 5) : 0u;
+        }
+#pragma unroll
+        for (int q = 0; q < BLK_CHUNK; ++q) {
+            const uint32_t t = static_cast<uint32_t>(tq[q]);
+            if ((wq[q] >> (t & 31)) & 1u) {
+                int j = -1;
+                uint32_t h = blk_hash(t);
+                for (;;) {
+                    const uint32_t key = ld_w(&bkey[h]);
+                    if (key == t) {
+                        j = static_cast<int>(ld_w(&bpos[h]));
+                        break;
+                    }
+                    if (key == BLK_EMPTY) break;
+                    h = (h + 1) & (BLK_BSLOTS - 1);
+                }
+                const bool rec = j < static_cast<int>(lane);
+                const int32_t val = j < 0 ? tq[q] : -(j + 1);
+#pragma unroll
+                for (int k = 0; k < BLK_K; ++k) nl[k] = (rec && cntn == k) ? val : nl[k];
+                cntn += rec ? 1 : 0;
+            }
+        }
+    }
+    bool bad = cntn > BLK_K;
+
+    // 3. roots of the earlier sites (first parent loads issued together), each
+    //    entered once into the root table; nl[k] becomes the neighbour's node
+    int32_t pv[BLK_K];
+#pragma unroll
+    for (int k = 0; k < BLK_K; ++k) pv[k] = (!bad && k < cntn && nl[k] >= 0) ? m.par_ld(lds, nl[k]) : -1;
+    int nnew = 0;
+#pragma unroll
+    for (int k = 0; k < BLK_K; ++k) {
+        if (!bad && k < cntn) {
+            if (nl[k] >= 0) {
+                int32_t root;
+                uint32_t word;
+                sweep_find_from<RES>(m, lds, nl[k], pv[k], root, word);
+                uint32_t h = blk_hash(static_cast<uint32_t>(root));
+                int slot = -1;
+                for (uint32_t t = 0; t < BLK_RSLOTS; ++t) {
+                    uint32_t expected = BLK_EMPTY;
+                    if (__hip_atomic_compare_exchange_strong(&rkey[h], &expected, static_cast<uint32_t>(root),
+                                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_WAVEFRONT)) {
+                        st_w(&nword[64 + h], word);
+                        slot = static_cast<int>(h);
+                        ++nnew;
+                        break;
+                    }
+                    if (expected == static_cast<uint32_t>(root)) {
+                        slot = static_cast<int>(h);
+                        break;
+                    }
+                    h = (h + 1) & (BLK_RSLOTS - 1);
+                }
+                bad = bad || slot < 0;
+                nl[k] = 64 + slot;
+            } else {
+                nl[k] = -nl[k] - 1;
+            }
+        }
+    }
+    // the roots entered by all lanes, against the cap on distinct roots
+    int nold = nnew;
+#pragma unroll
+    for (int d = 1; d < 64; d <<= 1) nold += __shfl_xor(nold, d);
+    if (__ballot(bad) || nold > max_old) {
+        if (act) m.occ_andn(lds, static_cast<uint32_t>(s) >> 5, 1u << (s & 31));
+        return BLK_FALLBACK;
+    }
+    __builtin_amdgcn_wave_barrier();
+
+    // 4. connected components: hook the worse root under the better one (larger
+    //    size, then larger node), until no edge joins two trees
+    for (;;) {
+        bool hooked = false;
+#pragma unroll
+        for (int k = 0; k < BLK_K; ++k) {
+            if (k < cntn) {
+                const uint32_t a = blk_find(npar, lane);
+                const uint32_t b = blk_find(npar, static_cast<uint32_t>(nl[k]));
+                if (a != b) {
+                    const uint32_t sa = ld_w(&nword[a]) & NZ_SIZE, sb = ld_w(&nword[b]) & NZ_SIZE;
+                    const bool a_up = sa > sb || (sa == sb && a > b);
+                    uint32_t expected = a_up ? b : a;
+                    __hip_atomic_compare_exchange_strong(&npar[expected], &expected, a_up ? a : b, __ATOMIC_RELAXED,
+                                                         __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    hooked = true;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+        if (!__ballot(hooked)) break;
+    }
+
+    // 5. sizes and flags into the roots; live nodes are the block's positions
+    //    and the occupied root-table slots
+    uint32_t nroot[BLK_NODES / 64];
+    bool nlive[BLK_NODES / 64];
+#pragma unroll
+    for (uint32_t q = 0; q < BLK_NODES / 64; ++q) {
+        const uint32_t n = lane + 64 * q;
+        nlive[q] = q == 0 ? act : ld_w(&rkey[n - 64]) != BLK_EMPTY;
+        nroot[q] = nlive[q] ? blk_find(npar, n) : n;
+        if (nlive[q] && nroot[q] != n) {
+            const uint32_t w = ld_w(&nword[n]);
+            __hip_atomic_fetch_add(&nword[nroot[q]], w & NZ_SIZE, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+            __hip_atomic_fetch_or(&nword[nroot[q]], w & NZ_FLAGS, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
+    }
+    __builtin_amdgcn_wave_barrier();
+    bool spans = false;
+#pragma unroll
+    for (uint32_t q = 0; q < BLK_NODES / 64; ++q) {
+        const uint32_t n = lane + 64 * q;
+        spans = spans || (nlive[q] && nroot[q] == n && (ld_w(&nword[n]) & NZ_FLAGS) == NZ_FLAGS);
+    }
+    if (__ballot(spans)) {
+        if (act) m.occ_andn(lds, static_cast<uint32_t>(s) >> 5, 1u << (s & 31));
+        return BLK_FALLBACK;
+    }
+
+    // 6. write back: roots get their root word, other nodes link to their root
+#pragma unroll
+    for (uint32_t q = 0; q < BLK_NODES / 64; ++q) {
+        const uint32_t n = lane + 64 * q;
+        const uint32_t r = nroot[q];
+        const int32_t rsite_pos = __shfl(s, static_cast<int>(r & 63));   // all lanes take part
+        if (nlive[q]) {
+            const int32_t site = q == 0 ? s : static_cast<int32_t>(ld_w(&rkey[n - 64]));
+            int32_t v;
+            if (r == n) v = static_cast<int32_t>(ld_w(&nword[n]));
+            else v = r < 64 ? rsite_pos : static_cast<int32_t>(ld_w(&rkey[r - 64]));
+            m.par_st(lds, site, v);
+        }
+    }
+    return BLK_COMMITTED;
+}
+
 struct SweepOut {
     int32_t *nstar;
     int32_t *mass;
     const int32_t *out_index; // per sample: position in the caller's output arrays
 };
 
-template <int NCH, int RES>
+template <int NCH, int RES, bool BLOCK>
 __global__ void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
 {
     extern __shared__ uint32_t lds[];
@@ -560,92 +979,97 @@ __global__ void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
             }
         }
 
-        const uint32_t *counts = reinterpret_cast<const uint32_t *>(a.ws + d.off_counts);
-        const uint32_t *sites = reinterpret_cast<const uint32_t *>(a.ws + d.off_sites);
         int32_t r = a.state[sid].n0;   // sites already occupied
         int32_t status = NZ_ST_BAND;
         int32_t nstar = 0, mass = 0;
 
-        for (int32_t b = 0; b < nb && status == NZ_ST_BAND; ++b) {
-            const uint32_t cnt = counts[b];
-            if (cnt > cap) {
-                status = NZ_ST_BUCKET;
-                break;
-            }
-            const uint32_t *bs = sites + static_cast<uint64_t>(b) * cap;
-            for (uint32_t j0 = 0; j0 < cnt && status == NZ_ST_BAND; j0 += 64) {
-                const uint32_t mine = (j0 + lane < cnt) ? bs[j0 + lane] : 0u;
-                const uint32_t mcount = min(64u, cnt - j0);
-                for (uint32_t jj = 0; jj < mcount; ++jj) {
-                    const uint32_t pc = bcast(mine, static_cast<int>(jj));
-                    const int32_t x0 = pc & 63, x1 = (pc >> 6) & 63, x2 = (pc >> 12) & 63, x3 = (pc >> 18) & 63,
-                                  x4 = pc >> 24;
-                    const int32_t s = x0 + L * (x1 + L * (x2 + L * (x3 + L * x4)));
-                    const uint32_t A = allowed_axis(x0, L) | (allowed_axis(x1, L) << 5) | (allowed_axis(x2, L) << 10) |
-                                       (allowed_axis(x3, L) << 15) | (allowed_axis(x4, L) << 20);
-                    const uint32_t fl = (x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u);
-                    ++r;
-
-                    // neighbour occupancy: issue every chunk's load before using any
-                    uint32_t word[NCH];
-                    int32_t tn[NCH];
-                    bool inb[NCH];
-                    const uint32_t own = m.occ_ld(lds, static_cast<uint32_t>(s) >> 5);
-#pragma unroll
-                    for (int c = 0; c < NCH; ++c) {
-                        inb[c] = (ocode[c] & ~A) == 0u;
-                        tn[c] = s + ostride[c];
-                        word[c] = inb[c] ? m.occ_ld(lds, static_cast<uint32_t>(tn[c]) >> 5) : 0u;
-                    }
-                    // all lanes store the same updated word of s (this wave is the
-                    // only writer of the sample's bitset)
-                    m.occ_st(lds, static_cast<uint32_t>(s) >> 5, own | (1u << (s & 31)));
-
-                    // distinct roots: lanes 0..D-1 hold (root, root word); entry 0 is s itself
-                    int32_t lroot = s;
-                    uint32_t lword = NZ_ROOT | fl | 1u;
-                    int D = 1;
-#pragma unroll
-                    for (int c = 0; c < NCH; ++c) {
-                        const bool o = inb[c] && ((word[c] >> (tn[c] & 31)) & 1u);
-                        uint64_t mk = __ballot(o);
-                        if (!mk) continue;
-                        int32_t root = 0;
-                        uint32_t rw = 0;
-                        if (o) sweep_find<RES>(m, lds, tn[c], root, rw);
-                        bool stale = false;   // a flush since these finds may have linked their roots
-                        while (mk) {
-                            const int l = __builtin_ctzll(mk);
-                            mk &= mk - 1;
-                            int32_t rr = bcast(root, l);
-                            uint32_t rrw = bcast(rw, l);
-                            if (stale) sweep_find<RES>(m, lds, rr, rr, rrw);
-                            if (__ballot(static_cast<int>(lane) < D && lroot == rr)) continue;
-                            if (D == dcap) {
-                                // list full: merge what we have and keep only the survivor;
-                                // rr is not in the list, so the flush leaves it a root
-                                uint32_t tot, flg;
-                                const int32_t w = sweep_merge<RES>(m, lds, D, lroot, lword, tot, flg);
-                                lroot = lane == 0 ? w : lroot;
-                                lword = lane == 0 ? (NZ_ROOT | flg | tot) : lword;
-                                D = 1;
-                                stale = true;
+        if constexpr (BLOCK) {
+            // 64 sites of the band at a time; blocks do not cross buckets
+            const uint32_t *counts = reinterpret_cast<const uint32_t *>(a.ws + d.off_counts);
+            const uint32_t *sites = reinterpret_cast<const uint32_t *>(a.ws + d.off_sites);
+            const uint32_t hbase = m.lbase + a.lds_words - BLK_LDS_WORDS;
+            SiteStep<NCH> cur;
+            bool done = false;
+            for (int32_t b = 0; b < nb && !done; ++b) {
+                const uint32_t cnt = counts[b];
+                if (cnt > cap) {
+                    status = NZ_ST_BUCKET;
+                    break;
+                }
+                const uint32_t *bs = sites + static_cast<uint64_t>(b) * cap;
+                for (uint32_t j0 = 0; j0 < cnt; j0 += 64) {
+                    const int nbk = static_cast<int>(min(64u, cnt - j0));
+                    const uint32_t pcl = static_cast<int>(lane) < nbk ? bs[j0 + lane] : 0u;
+                    const int res = block_step<RES>(m, lds, hbase, nbk, pcl, L, tab, z, a.blk_old);
+                    if (res == BLK_FALLBACK) {
+                        for (int i = 0; i < nbk; ++i) {
+                            ++r;
+                            cur.prepare(m, lds, bcast(pcl, i), L, ostride, ocode);
+                            uint32_t total, flags;
+                            sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
+                            if (flags == NZ_FLAGS) {
+                                status = NZ_ST_DONE;
+                                nstar = r;
+                                mass = static_cast<int32_t>(total);
+                                done = true;
+                                break;
                             }
-                            lroot = static_cast<int>(lane) == D ? rr : lroot;
-                            lword = static_cast<int>(lane) == D ? rrw : lword;
-                            ++D;
                         }
+                        if (done) break;
+                        continue;
                     }
-                    uint32_t total, flags;
-                    sweep_merge<RES>(m, lds, D, lroot, lword, total, flags);
-                    if (flags == NZ_FLAGS) {
-                        status = NZ_ST_DONE;
-                        nstar = r;
-                        mass = static_cast<int32_t>(total);
-                        break;
-                    }
+                    r += nbk;
                 }
             }
+        } else {
+        // The band in (key, site) order; the occupancy words of the next site are
+        // loaded while the current one is processed.  Only the current site can
+        // change them in between, so they are patched with its bit afterwards.
+        BandCursor bc;
+        bc.init(reinterpret_cast<const uint32_t *>(a.ws + d.off_counts),
+                reinterpret_cast<const uint32_t *>(a.ws + d.off_sites), cap, nb);
+        SiteStep<NCH> cur, nxt;
+        uint32_t pc = 0;
+        int got = bc.next(pc, lane);
+        if (got < 0) status = NZ_ST_BUCKET;
+        if constexpr (kLookahead<NCH>) {
+            if (got == 1) cur.prepare(m, lds, pc, L, ostride, ocode);
+            while (got == 1) {
+                ++r;
+                uint32_t pcn = 0;
+                const int gotn = bc.next(pcn, lane);
+                if (gotn == 1) nxt.prepare(m, lds, pcn, L, ostride, ocode);
+                uint32_t total, flags;
+                sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
+                if (flags == NZ_FLAGS) {
+                    status = NZ_ST_DONE;
+                    nstar = r;
+                    mass = static_cast<int32_t>(total);
+                    break;
+                }
+                if (gotn != 1) {
+                    if (gotn < 0) status = NZ_ST_BUCKET;
+                    break;
+                }
+                nxt.patch(cur.s);
+                cur = nxt;
+            }
+        } else {
+            while (got == 1) {
+                ++r;
+                cur.prepare(m, lds, pc, L, ostride, ocode);
+                uint32_t total, flags;
+                sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
+                if (flags == NZ_FLAGS) {
+                    status = NZ_ST_DONE;
+                    nstar = r;
+                    mass = static_cast<int32_t>(total);
+                    break;
+                }
+                got = bc.next(pc, lane);
+                if (got < 0) status = NZ_ST_BUCKET;
+            }
+        }
         }
         if (status == NZ_ST_BAND && d.full) {
             status = NZ_ST_DONE;   // the whole lattice is occupied and never spans
@@ -718,11 +1142,11 @@ hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nli
     return hipGetLastError();
 }
 
-template <int NCH, int RES>
+template <int NCH, int RES, bool BLOCK>
 static hipError_t launch_sweep_t(const NzSweepArgs &a, const SweepOut &o, int grid, int wg_waves, size_t lds,
                                  hipStream_t st)
 {
-    auto k = nz_sweep_kernel<NCH, RES>;
+    auto k = nz_sweep_kernel<NCH, RES, BLOCK>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(lds));
@@ -732,29 +1156,39 @@ static hipError_t launch_sweep_t(const NzSweepArgs &a, const SweepOut &o, int gr
     return hipGetLastError();
 }
 
-template <int RES>
+template <int RES, bool BLOCK>
 static hipError_t launch_sweep_r(int nch, const NzSweepArgs &a, const SweepOut &o, int grid, int wg_waves, size_t lds,
                                  hipStream_t st)
 {
     switch (nch) {
-    case 1: return launch_sweep_t<1, RES>(a, o, grid, wg_waves, lds, st);
-    case 2: return launch_sweep_t<2, RES>(a, o, grid, wg_waves, lds, st);
-    case 4: return launch_sweep_t<4, RES>(a, o, grid, wg_waves, lds, st);
-    case 8: return launch_sweep_t<8, RES>(a, o, grid, wg_waves, lds, st);
-    case 14: return launch_sweep_t<14, RES>(a, o, grid, wg_waves, lds, st);
+    case 1: return launch_sweep_t<1, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
+    case 2: return launch_sweep_t<2, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
+    case 4: return launch_sweep_t<4, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
+    case 8: return launch_sweep_t<8, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
+    case 14: return launch_sweep_t<14, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
     default: return hipErrorInvalidValue;
     }
 }
 
-hipError_t launch_sweep(int nch, int residency, const NzSweepArgs &a, int32_t *nstar, int32_t *mass,
+uint32_t block_lds_words() { return BLK_LDS_WORDS; }
+
+hipError_t launch_sweep(int nch, int residency, bool block, const NzSweepArgs &a, int32_t *nstar, int32_t *mass,
                         const int32_t *out_index, int grid, int wg_waves, hipStream_t st)
 {
     SweepOut o{nstar, mass, out_index};
     const size_t lds = static_cast<size_t>(a.lds_words) * 4u * static_cast<size_t>(wg_waves);
+    if (block) {
+        switch (residency) {
+        case RES_HBM: return launch_sweep_r<RES_HBM, true>(nch, a, o, grid, wg_waves, lds, st);
+        case RES_OCC: return launch_sweep_r<RES_OCC, true>(nch, a, o, grid, wg_waves, lds, st);
+        case RES_ALL: return launch_sweep_r<RES_ALL, true>(nch, a, o, grid, wg_waves, lds, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     switch (residency) {
-    case RES_HBM: return launch_sweep_r<RES_HBM>(nch, a, o, grid, wg_waves, lds, st);
-    case RES_OCC: return launch_sweep_r<RES_OCC>(nch, a, o, grid, wg_waves, lds, st);
-    case RES_ALL: return launch_sweep_r<RES_ALL>(nch, a, o, grid, wg_waves, lds, st);
+    case RES_HBM: return launch_sweep_r<RES_HBM, false>(nch, a, o, grid, wg_waves, lds, st);
+    case RES_OCC: return launch_sweep_r<RES_OCC, false>(nch, a, o, grid, wg_waves, lds, st);
+    case RES_ALL: return launch_sweep_r<RES_ALL, false>(nch, a, o, grid, wg_waves, lds, st);
     default: return hipErrorInvalidValue;
     }
 }

@@ -25,8 +25,10 @@ hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nli
                           const NzOffset *tabs, uint8_t *ws, NzState *state, hipStream_t st);
 
 // residency: 0 HBM, 1 bitset in LDS, 2 bitset and parents in LDS.
-// nch in {1, 2, 4, 8, 14}.
-hipError_t launch_sweep(int nch, int residency, const NzSweepArgs &a, int32_t *nstar, int32_t *mass,
+// nch in {1, 2, 4, 8, 14}.  block: 64 sites per wave step (the wave's LDS
+// slice must end with block_lds_words() words for the block's site table).
+hipError_t launch_sweep(int nch, int residency, bool block, const NzSweepArgs &a, int32_t *nstar, int32_t *mass,
                         const int32_t *out_index, int grid, int wg_waves, hipStream_t st);
+uint32_t block_lds_words();
 
 }  // namespace nz

@@ -44,7 +44,8 @@ class NzJob(ctypes.Structure):
 
 class NzTuning(ctypes.Structure):
     _fields_ = [("residency", ctypes.c_int32), ("wg_waves", ctypes.c_int32),
-                ("waves_per_simd", ctypes.c_int32), ("bucket_log2", ctypes.c_int32)]
+                ("waves_per_simd", ctypes.c_int32), ("bucket_log2", ctypes.c_int32),
+                ("sweep_mode", ctypes.c_int32)]
 
 
 class NzError(RuntimeError):
@@ -171,6 +172,7 @@ def make_tuning(tune) -> NzTuning | None:
     t.wg_waves = int(tune.get("wg_waves", 0))
     t.waves_per_simd = int(tune.get("waves_per_simd", 0))
     t.bucket_log2 = int(tune.get("bucket_log2", 0))
+    t.sweep_mode = int(tune.get("sweep_mode", 0))
     return t
 
 

@@ -87,6 +87,8 @@ def test_prefix_list_redo():
 @pytest.mark.parametrize("tune", [
     dict(residency=1), dict(residency=3), dict(residency=2, wg_waves=1), dict(wg_waves=2, waves_per_simd=2),
     dict(wg_waves=8), dict(bucket_log2=4), dict(bucket_log2=10), dict(residency=1, wg_waves=2),
+    dict(sweep_mode=1), dict(sweep_mode=2), dict(sweep_mode=1, residency=1), dict(sweep_mode=1, residency=3),
+    dict(sweep_mode=2, residency=3), dict(sweep_mode=2, residency=1, wg_waves=4),
 ])
 def test_tuning_never_changes_results(tune):
     jobs = [dict(L=L, zone_mask=m, seed=99, nsamples=10) for L in (4, 6, 8) for m in (1, 0x07, 0x7F)]
@@ -99,6 +101,33 @@ def test_early_merge_path():
     with env(NZ_DEBUG_DCAP=2):
         gn, gm, _, _ = run_batch(jobs)
     assert_same(jobs, gn, gm, *oracle_batch(jobs))
+
+
+@pytest.mark.parametrize("cap", [0, 3])
+@pytest.mark.parametrize("residency", [0, 1])
+def test_block_fallback_path(cap, residency):
+    """Blocks that touch more earlier roots than allowed are redone one site at
+    a time; plain and prefilled samples, sparse and dense neighbourhoods."""
+    jobs = [dict(L=L, zone_mask=m, seed=47, nsamples=10) for L in (5, 8) for m in (1, 0x0C, 0x7F)]
+    jobs += [dict(L=8, zone_mask=m, seed=48, nsamples=10, n0=n0, backoff=200) for m, n0 in ((1, 3000), (0x03, 900))]
+    with env(NZ_DEBUG_BLOCK_OLD=cap):
+        gn, gm, _, _ = run_batch(jobs, tune=dict(sweep_mode=2, residency=residency))
+    assert_same(jobs, gn, gm, *oracle_batch(jobs))
+
+
+@pytest.mark.parametrize("L", [9, 12])
+def test_block_matches_single_site(L):
+    """The 64-site block sweep and the one-site sweep agree sample by sample on
+    prefilled runs of every compact neighbourhood (no oracle: too large)."""
+    from paper_2607_18991_amd import learned
+
+    model = learned.PrefillModel.load()
+    jobs = [dict(L=L, zone_mask=m, seed=1200 + L, nsamples=24) for m in COMPACT]
+    jobs = model.plan(jobs)
+    a = run_batch(jobs, tune=dict(sweep_mode=1))
+    b = run_batch(jobs, tune=dict(sweep_mode=2))
+    assert (a[0] == b[0]).all() and (a[1] == b[1]).all()
+    assert (a[0] > 0).all()
 
 
 def test_small_workspace_chunks():
