@@ -18,8 +18,9 @@
  * Conventions shared by every entry point:
  *   - site i has coordinates x_j = floor(i / L^j) mod L (x0 fastest);
  *   - the occupation order of sample s under seed is the sites sorted by
- *     (K(i), i), K(i) = (w1 << 32) | w0 where (w0..w3) = Philox4x32-10 of
- *     counter (i, lo32(s), hi32(s), 0) under key (lo32(seed), hi32(seed));
+ *     (K(i), i), where (w0..w3) = Philox4x32-10 of counter (floor(i / 2),
+ *     lo32(s), hi32(s), 0) under key (lo32(seed), hi32(seed)) and
+ *     K(i) = (w1 << 32) | w0 for even i, (w3 << 32) | w2 for odd i;
  *   - n* (1-based) is the number of occupied sites when a spanning cluster first
  *     exists, mass its size at that moment; n* = mass = 0 when even the full
  *     lattice does not span (only L = 2 with zones 6 and/or 7 alone).
@@ -122,9 +123,11 @@ typedef struct {
  *   waves_per_simd  resident sweep waves per SIMD of the persistent launch.
  *   bucket_log2     log2 of the mean number of keys per sort bucket (4..10).
  *   sweep_mode      1: one site per wave step (z lanes check the neighbours);
- *                   2: 64 sites per wave step (one site per lane, unions
- *                   replayed in order on a register union-find; a block that
- *                   does not fit it is redone one site at a time).
+ *                   2: 64 sites per wave step (one site per lane; the block's
+ *                   unions are merged by a connected-components pass in LDS;
+ *                   the block in which spanning first occurs, and a block
+ *                   that does not fit the LDS tables, is redone one site at a
+ *                   time).
  */
 typedef struct {
     int32_t residency;

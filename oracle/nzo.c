@@ -84,12 +84,15 @@ void nzo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = c0; out[1] = c1; out[2] = c2; out[3] = c3;
 }
 
+/* Sites 2j and 2j + 1 share the Philox block of counter j: the even site takes
+ * words (1, 0), the odd site words (3, 2). */
 uint64_t nzo_key(uint64_t seed, uint64_t sample, uint32_t site, uint32_t tag)
 {
-    uint32_t ctr[4] = { site, (uint32_t)sample, (uint32_t)(sample >> 32), tag };
+    uint32_t ctr[4] = { site >> 1, (uint32_t)sample, (uint32_t)(sample >> 32), tag };
     uint32_t key[2] = { (uint32_t)seed, (uint32_t)(seed >> 32) };
     uint32_t out[4];
     nzo_philox4x32_10(ctr, key, out);
+    if (site & 1u) return ((uint64_t)out[3] << 32) | (uint64_t)out[2];
     return ((uint64_t)out[1] << 32) | (uint64_t)out[0];
 }
 

@@ -43,8 +43,9 @@ int nzo_offsets(uint32_t mask, int32_t *d);
 void nzo_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
 
 /* 64-bit key of site i for (seed, sample) with domain tag 0:
- * key words (lo32(seed), hi32(seed)), counter (i, lo32(sample), hi32(sample), tag),
- * K = (out1 << 32) | out0. */
+ * key words (lo32(seed), hi32(seed)), counter (floor(i / 2), lo32(sample),
+ * hi32(sample), tag); K = (out1 << 32) | out0 for even i, (out3 << 32) | out2
+ * for odd i (one Philox block serves two neighbouring sites). */
 uint64_t nzo_key(uint64_t seed, uint64_t sample, uint32_t site, uint32_t tag);
 
 /* order[0..n) = indices 0..n-1 sorted ascending by (keys[i], i).  Returns 0 or -1. */

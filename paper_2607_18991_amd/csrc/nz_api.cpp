@@ -442,7 +442,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             size_t off = head;
             int32_t max_nb = 0, max_cap = 0, max_z = 0;
             uint32_t max_N = 0;
-            int64_t max_hook = 0, max_site = 0;
+            int64_t max_site = 0;
             std::vector<int32_t> desc_of_chunk(n);
             for (int32_t di = 0; di < n; ++di) {
                 const int32_t ci = byL[di];
@@ -478,7 +478,6 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 max_N = std::max(max_N, static_cast<uint32_t>(d.N));
                 if (d.T0 != 0) {
                     prefill_list.push_back(di);
-                    max_hook = std::max<int64_t>(max_hook, static_cast<int64_t>(s.prefix_cap) * (d.z / 2));
                     max_site = std::max<int64_t>(max_site, s.prefix_cap);
                 }
             }
@@ -526,7 +525,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             }
             if (pe) HIP_TRY(hipEventRecord(pe->ev[1], st));
             if (!prefill_list.empty()) {
-                const int32_t bx_hook = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(2048, (max_hook + 1023) / 1024)));
+                const int32_t bx_hook = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(256, (max_site + 1023) / 1024)));
                 const int32_t bx_site = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(1024, (max_site + 1023) / 1024)));
                 HIP_TRY(nz::launch_prefill(d_desc, d_list, static_cast<int32_t>(prefill_list.size()), bx_hook, bx_site, d_tabs, ws,
                                            d_state, st));

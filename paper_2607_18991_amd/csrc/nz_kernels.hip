@@ -37,25 +37,27 @@ constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
 constexpr uint32_t kWeylA = 0x9E3779B9u;
 constexpr uint32_t kWeylB = 0xBB67AE85u;
 
-__device__ __forceinline__ uint64_t site_key(uint32_t seed_lo, uint32_t seed_hi,
-                                             uint32_t smp_lo, uint32_t smp_hi, uint32_t site)
+// Keys of sites 2j and 2j + 1: both come from the block of counter j (word 3:
+// domain tag 0); the even site takes words (1, 0), the odd site words (3, 2).
+// Each round's two 32x32 products are formed as full 64-bit products.
+__device__ __forceinline__ void site_key_pair(uint32_t seed_lo, uint32_t seed_hi, uint32_t smp_lo, uint32_t smp_hi,
+                                              uint32_t j, uint64_t &k_even, uint64_t &k_odd)
 {
-    uint32_t c0 = site, c1 = smp_lo, c2 = smp_hi, c3 = 0u;  // word 3: domain tag 0
+    uint32_t c0 = j, c1 = smp_lo, c2 = smp_hi, c3 = 0u;
     uint32_t k0 = seed_lo, k1 = seed_hi;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint32_t a_hi = __umulhi(kPhiloxMulA, c0);
-        const uint32_t a_lo = kPhiloxMulA * c0;
-        const uint32_t b_hi = __umulhi(kPhiloxMulB, c2);
-        const uint32_t b_lo = kPhiloxMulB * c2;
-        c0 = b_hi ^ c1 ^ k0;
-        c1 = b_lo;
-        c2 = a_hi ^ c3 ^ k1;
-        c3 = a_lo;
+        const uint64_t a = static_cast<uint64_t>(kPhiloxMulA) * c0;
+        const uint64_t b = static_cast<uint64_t>(kPhiloxMulB) * c2;
+        c0 = static_cast<uint32_t>(b >> 32) ^ c1 ^ k0;
+        c1 = static_cast<uint32_t>(b);
+        c2 = static_cast<uint32_t>(a >> 32) ^ c3 ^ k1;
+        c3 = static_cast<uint32_t>(a);
         k0 += kWeylA;
         k1 += kWeylB;
     }
-    return (static_cast<uint64_t>(c1) << 32) | c0;
+    k_even = (static_cast<uint64_t>(c1) << 32) | c0;
+    k_odd = (static_cast<uint64_t>(c3) << 32) | c2;
 }
 
 // floor(n / L) for n < 2^32 with magic = ceil(2^64 / L) (0 for L = 1).
@@ -128,84 +130,190 @@ __global__ __launch_bounds__(256) void nz_clear_kernel(const NzSample *__restric
 
 // ---------------------------------------------------------------------------
 // Keys, prefill occupancy and band bucketing.  A block covers
-// KEYS_THREADS * KEYS_ITERS consecutive sites of one sample; each wave handles
-// 64 consecutive sites per iteration so that a ballot yields two bitset words.
+// KEYS_THREADS * 2 * KEYS_ITERS consecutive sites of one sample; per iteration
+// each wave takes 128 consecutive sites, lane l the pair (2l, 2l + 1) that
+// shares one Philox block, so two ballots yield four bitset words.
 
 constexpr int KEYS_THREADS = 256;
-constexpr int KEYS_ITERS = 16;
-constexpr int KEYS_SITES_PER_BLOCK = KEYS_THREADS * KEYS_ITERS;
+constexpr int KEYS_ITERS = 8;
+constexpr int KEYS_SITES_PER_BLOCK = KEYS_THREADS * 2 * KEYS_ITERS;
+
+// The 16 bits of x moved to the even bit positions of a 32-bit word.
+__device__ __forceinline__ uint32_t spread_even(uint32_t x)
+{
+    x = (x | (x << 8)) & 0x00FF00FFu;
+    x = (x | (x << 4)) & 0x0F0F0F0Fu;
+    x = (x | (x << 2)) & 0x33333333u;
+    x = (x | (x << 1)) & 0x55555555u;
+    return x;
+}
+
+struct KeysCtx {
+    uint64_t T0;
+    int32_t shift;
+    uint64_t nb;
+    uint32_t cap;
+    uint32_t L;
+    uint64_t magic;
+    int32_t *par;
+    uint64_t *keys;
+    uint32_t *sites;
+    uint32_t *counts;
+};
+
+// Band sites of a wave are queued in LDS and bucketed 64 at a time, one per
+// lane, so the bucketing work runs on full waves although only a few percent of
+// the sites fall into the band.
+constexpr uint32_t KEYS_BQ = 192;   // queue entries per wave (< 64 left + 128 new)
+
+__device__ __forceinline__ void keys_bucket(const KeysCtx &c, uint64_t K, uint32_t i)
+{
+    const uint64_t b = (K - c.T0) >> c.shift;
+    const uint32_t slot = atomicAdd(&c.counts[b], 1u);
+    if (slot < c.cap) {
+        c.keys[b * c.cap + slot] = K;
+        c.sites[b * c.cap + slot] = pack_coords(i, c.L, c.magic);
+    }
+}
 
 __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *__restrict__ desc,
                                                                const int32_t *__restrict__ list, int32_t first,
                                                                int32_t blocks_per_sample, uint8_t *__restrict__ ws,
                                                                NzState *__restrict__ state)
 {
-    // prefilled sites of this block, staged in LDS and appended to the
-    // sample's list with one global atomic per block
+    // prefilled sites of this block, staged in LDS (one slice per wave, filled
+    // in ballot order without atomics) and appended to the sample's list with
+    // one global atomic per block
+    constexpr uint32_t kSlice = KEYS_SITES_PER_BLOCK / (KEYS_THREADS / 64);
     __shared__ uint32_t pre_sites[KEYS_SITES_PER_BLOCK];
-    __shared__ uint32_t pre_count, pre_base;
+    __shared__ uint32_t pre_count[KEYS_THREADS / 64];
+    __shared__ uint32_t pre_base;
+    __shared__ uint64_t bq_key[KEYS_THREADS / 64][KEYS_BQ];
+    __shared__ uint32_t bq_site[KEYS_THREADS / 64][KEYS_BQ];
     const int which = static_cast<int>(blockIdx.x) / blocks_per_sample;
     const int sid = list ? list[first + which] : first + which;
     const int blk = static_cast<int>(blockIdx.x) % blocks_per_sample;
     const NzSample &d = desc[sid];
     const uint32_t N = static_cast<uint32_t>(d.N);
-    const uint32_t L = static_cast<uint32_t>(d.L);
-    const uint64_t magic = d.magic;
-    const uint64_t T0 = d.T0;
-    const int32_t shift = d.shift;
-    const uint64_t nb = static_cast<uint64_t>(d.nb);
-    const uint32_t cap = static_cast<uint32_t>(d.cap);
     const uint32_t seed_lo = static_cast<uint32_t>(d.seed), seed_hi = static_cast<uint32_t>(d.seed >> 32);
     const uint32_t smp_lo = static_cast<uint32_t>(d.sample), smp_hi = static_cast<uint32_t>(d.sample >> 32);
+    const uint32_t occ_words = ((N + 63u) >> 6) << 1;   // padded to whole 64-site words
 
+    KeysCtx c;
+    c.T0 = d.T0;
+    c.shift = d.shift;
+    c.nb = static_cast<uint64_t>(d.nb);
+    c.cap = static_cast<uint32_t>(d.cap);
+    c.L = static_cast<uint32_t>(d.L);
+    c.magic = d.magic;
+    c.par = reinterpret_cast<int32_t *>(ws + d.off_par);
+    c.keys = reinterpret_cast<uint64_t *>(ws + d.off_keys);
+    c.sites = reinterpret_cast<uint32_t *>(ws + d.off_sites);
+    c.counts = reinterpret_cast<uint32_t *>(ws + d.off_counts);
     uint32_t *occ = reinterpret_cast<uint32_t *>(ws + d.off_occ);
-    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
-    uint64_t *keys = reinterpret_cast<uint64_t *>(ws + d.off_keys);
-    uint32_t *sites = reinterpret_cast<uint32_t *>(ws + d.off_sites);
-    uint32_t *counts = reinterpret_cast<uint32_t *>(ws + d.off_counts);
     uint32_t *prefix = reinterpret_cast<uint32_t *>(ws + d.off_prefix);
+    // keys in [T0, band_end) fall into the band (band_end saturates at 2^64)
+    const uint64_t span = c.nb << c.shift;
+    const bool band_all = c.shift >= 64 || (span >> c.shift) != c.nb || c.T0 + span < c.T0;
+    const uint64_t band_end = c.T0 + span;
 
     const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x >> 6;
+    uint32_t *slice = pre_sites + wave * kSlice;
+    uint64_t *qk = bq_key[wave];
+    uint32_t *qs = bq_site[wave];
+    uint32_t nstaged = 0;   // wave-uniform
+    uint32_t nq = 0;        // wave-uniform
     const uint32_t block_base = static_cast<uint32_t>(blk) * KEYS_SITES_PER_BLOCK;
-    if (threadIdx.x == 0) pre_count = 0u;
-    __syncthreads();
     for (int it = 0; it < KEYS_ITERS; ++it) {
-        const uint32_t wbase = block_base + it * KEYS_THREADS + (threadIdx.x & ~63u);
+        const uint32_t wbase = block_base + it * (2 * KEYS_THREADS) + 2u * (threadIdx.x & ~63u);
         if (wbase >= N) break;
-        const uint32_t i = wbase + lane;
-        const bool valid = i < N;
-        const uint64_t K = site_key(seed_lo, seed_hi, smp_lo, smp_hi, i);
-        const bool pre = valid && K < T0;
-        const uint64_t bal = __ballot(pre);
-        // Every lane stores: even lanes the low word, odd lanes the high word of
-        // the ballot (identical values per address).  No lane-conditional block
-        // sits next to a cross-lane operation inside this loop.  The bitset is
-        // padded to whole 64-site words, so both words exist.
-        occ[(wbase >> 5) + (lane & 1u)] = static_cast<uint32_t>(bal >> (32u * (lane & 1u)));
-        if (pre) {
-            par[i] = static_cast<int32_t>(i);
-            pre_sites[atomicAdd(&pre_count, 1u)] = i;
+        const uint32_t i0 = wbase + 2u * lane, i1 = i0 + 1u;
+        uint64_t K0, K1;
+        site_key_pair(seed_lo, seed_hi, smp_lo, smp_hi, i0 >> 1, K0, K1);
+        const bool v0 = i0 < N, v1 = i1 < N;
+        const bool pre0 = v0 && K0 < c.T0, pre1 = v1 && K1 < c.T0;
+        const bool band0 = v0 && !pre0 && (band_all || K0 < band_end);
+        const bool band1 = v1 && !pre1 && (band_all || K1 < band_end);
+        const uint64_t be = __ballot(pre0);
+        const uint64_t bo = __ballot(pre1);
+        const uint64_t qe = __ballot(band0);
+        const uint64_t qo = __ballot(band1);
+        // Word q of the four covering sites wbase .. wbase + 127 interleaves
+        // bits 16q .. 16q + 15 of the even and odd ballots.  Every lane stores
+        // (word lane & 3, identical values per address); words past the padded
+        // bitset are not stored.
+        const uint32_t q = lane & 3u;
+        const uint32_t e16 = static_cast<uint32_t>(be >> (16u * q)) & 0xFFFFu;
+        const uint32_t o16 = static_cast<uint32_t>(bo >> (16u * q)) & 0xFFFFu;
+        const uint32_t widx = (wbase >> 5) + q;
+        if (widx < occ_words) occ[widx] = spread_even(e16) | (spread_even(o16) << 1);
+        // prefilled: parent = itself, staged even sites first, then odd
+        const uint32_t ne = static_cast<uint32_t>(__popcll(be));
+        if (pre0) {
+            c.par[i0] = static_cast<int32_t>(i0);
+            slice[nstaged + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(be >> 32),
+                                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(be), 0u))] = i0;
         }
-        if (valid && !pre) {
-            const uint64_t b = (K - T0) >> shift;
-            if (b < nb) {
-                const uint32_t slot = atomicAdd(&counts[b], 1u);
-                if (slot < cap) {
-                    keys[b * cap + slot] = K;
-                    sites[b * cap + slot] = pack_coords(i, L, magic);
-                }
+        if (pre1) {
+            c.par[i1] = static_cast<int32_t>(i1);
+            slice[nstaged + ne + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(bo >> 32),
+                                                           __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bo), 0u))] = i1;
+        }
+        nstaged += ne + static_cast<uint32_t>(__popcll(bo));
+        // band: queued, then bucketed in full waves
+        const uint32_t nqe = static_cast<uint32_t>(__popcll(qe));
+        if (band0) {
+            const uint32_t e = nq + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(qe >> 32),
+                                                              __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(qe), 0u));
+            qk[e] = K0;
+            qs[e] = i0;
+        }
+        if (band1) {
+            const uint32_t e = nq + nqe + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(qo >> 32),
+                                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(qo), 0u));
+            qk[e] = K1;
+            qs[e] = i1;
+        }
+        nq += nqe + static_cast<uint32_t>(__popcll(qo));
+        __builtin_amdgcn_wave_barrier();
+        if (nq >= 64u) {
+            uint32_t base = 0;
+            for (; base + 64u <= nq; base += 64u) keys_bucket(c, qk[base + lane], qs[base + lane]);
+            // move the remainder (< 64 entries) to the front
+            const uint32_t rest = nq - base;
+            uint64_t rk = 0;
+            uint32_t rs = 0;
+            if (lane < rest) {
+                rk = qk[base + lane];
+                rs = qs[base + lane];
             }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < rest) {
+                qk[lane] = rk;
+                qs[lane] = rs;
+            }
+            __builtin_amdgcn_wave_barrier();
+            nq = rest;
         }
     }
+    if (lane < nq) keys_bucket(c, qk[lane], qs[lane]);
+    if (lane == 0) pre_count[wave] = nstaged;
     __syncthreads();
-    const uint32_t cnt = pre_count;
+    uint32_t cnt = 0;
+#pragma unroll
+    for (int w = 0; w < KEYS_THREADS / 64; ++w) cnt += pre_count[w];
     if (cnt) {
         if (threadIdx.x == 0) pre_base = atomicAdd(reinterpret_cast<uint32_t *>(&state[sid].n0), cnt);
         __syncthreads();
-        const uint32_t base = pre_base;
-        for (uint32_t k = threadIdx.x; k < cnt; k += KEYS_THREADS) {
-            const uint32_t pos = base + k;
-            if (pos < static_cast<uint32_t>(d.prefix_cap)) prefix[pos] = pre_sites[k];
+        uint32_t base = pre_base;
+        for (int w = 0; w < KEYS_THREADS / 64; ++w) {
+            const uint32_t n = pre_count[w];
+            for (uint32_t k = threadIdx.x; k < n; k += KEYS_THREADS) {
+                const uint32_t pos = base + k;
+                if (pos < static_cast<uint32_t>(d.prefix_cap)) prefix[pos] = pre_sites[w * kSlice + k];
+            }
+            base += n;
         }
     }
 }
@@ -294,43 +402,76 @@ __device__ __forceinline__ int32_t cc_find(int32_t *par, int32_t x)
     return x;
 }
 
-__global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
-                                                      const NzOffset *__restrict__ tabs, uint8_t *__restrict__ ws,
-                                                      NzState *__restrict__ state)
+// Workgroup l of a prefill launch covers block x of sample slot y.  The
+// workgroups of one sample share l mod 8, so they are dispatched to the same
+// XCD and the sample's bitset and parents stay in that XCD's L2.
+__device__ __forceinline__ bool xcd_slot(int32_t nlist, int32_t bx, int32_t &y, int32_t &x)
 {
-    const int sid = list[blockIdx.y];
+    const uint32_t l = blockIdx.x;
+    const uint32_t k = l >> 3;
+    y = static_cast<int32_t>((k / static_cast<uint32_t>(bx)) * 8u + (l & 7u));
+    x = static_cast<int32_t>(k % static_cast<uint32_t>(bx));
+    return y < nlist;
+}
+
+// Hook: one thread per prefilled site and its forward half of the offset
+// table (one of each +-d pair), eight neighbour words loaded at a time.
+constexpr int HOOK_UNROLL = 8;
+
+__global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
+                                                      int32_t nlist, int32_t bx, const NzOffset *__restrict__ tabs,
+                                                      uint8_t *__restrict__ ws, NzState *__restrict__ state)
+{
+    int32_t y, x;
+    if (!xcd_slot(nlist, bx, y, x)) return;
+    const int sid = list[y];
     const NzSample &d = desc[sid];
     const int32_t n0 = state[sid].n0;
     if (n0 > d.prefix_cap) return;
     const int32_t L = d.L;
-    const int32_t zh = d.z >> 1;        // the first half of a table holds one of each +-d pair
+    const int32_t zh = d.z >> 1;
     const uint64_t magic = d.magic;
     int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
     const uint32_t *occ = reinterpret_cast<const uint32_t *>(ws + d.off_occ);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
     const NzOffset *tab = tabs + d.tab;
-    const int64_t items = static_cast<int64_t>(n0) * zh;
-    for (int64_t it = static_cast<int64_t>(blockIdx.x) * blockDim.x + threadIdx.x; it < items;
-         it += static_cast<int64_t>(gridDim.x) * blockDim.x) {
-        const int32_t s = static_cast<int32_t>(prefix[it / zh]);
-        const NzOffset o = tab[it % zh];
+    for (int32_t i = x * 256 + static_cast<int32_t>(threadIdx.x); i < n0; i += bx * 256) {
+        const int32_t s = static_cast<int32_t>(prefix[i]);
         const uint32_t pc = pack_coords(static_cast<uint32_t>(s), static_cast<uint32_t>(L), magic);
         const uint32_t A = allowed_axis(pc & 63, L) | (allowed_axis((pc >> 6) & 63, L) << 5) |
                            (allowed_axis((pc >> 12) & 63, L) << 10) | (allowed_axis((pc >> 18) & 63, L) << 15) |
                            (allowed_axis(pc >> 24, L) << 20);
-        if (o.code & ~A) continue;
-        const int32_t t = s + o.stride;
-        if (!((occ[t >> 5] >> (t & 31)) & 1u)) continue;
-        int32_t u = cc_find(par, s);
-        int32_t v = cc_find(par, t);
-        while (u != v) {
-            if (u < v) { const int32_t w = u; u = v; v = w; }
-            int32_t expected = u;
-            if (__hip_atomic_compare_exchange_strong(&par[u], &expected, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                     __HIP_MEMORY_SCOPE_AGENT))
-                break;
-            u = cc_find(par, expected);
-            v = cc_find(par, v);
+        for (int32_t k0 = 0; k0 < zh; k0 += HOOK_UNROLL) {
+            int32_t t[HOOK_UNROLL];
+            uint32_t w[HOOK_UNROLL];
+#pragma unroll
+            for (int q = 0; q < HOOK_UNROLL; ++q) {
+                NzOffset o;
+                o.stride = 0;
+                o.code = 0xFFFFFFFFu;
+                if (k0 + q < zh) o = tab[k0 + q];
+                t[q] = s + o.stride;
+                w[q] = (o.code & ~A) == 0u ? occ[static_cast<uint32_t>(t[q]) >> 5] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < HOOK_UNROLL; ++q) {
+                if (!((w[q] >> (t[q] & 31)) & 1u)) continue;
+                int32_t u = cc_find(par, s);
+                int32_t v = cc_find(par, t[q]);
+                while (u != v) {
+                    if (u < v) {
+                        const int32_t tmp = u;
+                        u = v;
+                        v = tmp;
+                    }
+                    int32_t expected = u;
+                    if (__hip_atomic_compare_exchange_strong(&par[u], &expected, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT))
+                        break;
+                    u = cc_find(par, expected);
+                    v = cc_find(par, v);
+                }
+            }
         }
     }
 }
@@ -348,16 +489,19 @@ __device__ __forceinline__ uint32_t border_flags(uint32_t s, uint32_t L, uint64_
 // ancestor.  Roots never change in this kernel, so a walk stops at an entry that
 // points to itself or already holds a root word.
 __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
-                                                          uint8_t *__restrict__ ws, NzState *__restrict__ state)
+                                                          int32_t nlist, int32_t bx, uint8_t *__restrict__ ws,
+                                                          NzState *__restrict__ state)
 {
-    const int sid = list[blockIdx.y];
+    int32_t y, x;
+    if (!xcd_slot(nlist, bx, y, x)) return;
+    const int sid = list[y];
     const NzSample &d = desc[sid];
     const int32_t n0 = state[sid].n0;
     if (n0 > d.prefix_cap) return;
     const uint32_t L = static_cast<uint32_t>(d.L);
     int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
-    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n0; k += gridDim.x * blockDim.x) {
+    for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
         const int32_t s = static_cast<int32_t>(prefix[k]);
         int32_t r = s;
         int32_t p = ld_a(&par[r]);
@@ -380,19 +524,22 @@ __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__rest
 // completes a root's pair of border flags sees it: the state already spans and
 // the sample backs off.
 __global__ __launch_bounds__(256) void nz_accum_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
-                                                       uint8_t *__restrict__ ws, NzState *__restrict__ state)
+                                                       int32_t nlist, int32_t bx, uint8_t *__restrict__ ws,
+                                                       NzState *__restrict__ state)
 {
-    const int sid = list[blockIdx.y];
+    int32_t y, x;
+    if (!xcd_slot(nlist, bx, y, x)) return;
+    const int sid = list[y];
     const NzSample &d = desc[sid];
     const int32_t n0 = state[sid].n0;
     if (n0 > d.prefix_cap) {
-        if (blockIdx.x == 0 && threadIdx.x == 0) state[sid].status = NZ_ST_PREFIX;
+        if (x == 0 && threadIdx.x == 0) state[sid].status = NZ_ST_PREFIX;
         return;
     }
     const uint32_t L = static_cast<uint32_t>(d.L);
     int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
-    for (int32_t k = blockIdx.x * blockDim.x + threadIdx.x; k < n0; k += gridDim.x * blockDim.x) {
+    for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
         const int32_t s = static_cast<int32_t>(prefix[k]);
         const int32_t r = par[s];
         if (r >= 0) {
@@ -1136,9 +1283,13 @@ hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nli
                           const NzOffset *tabs, uint8_t *ws, NzState *state, hipStream_t st)
 {
     if (nlist <= 0) return hipSuccess;
-    hipLaunchKernelGGL(nz_hook_kernel, dim3(bx_hook, nlist), dim3(256), 0, st, desc, list, tabs, ws, state);
-    hipLaunchKernelGGL(nz_compress_kernel, dim3(bx_site, nlist), dim3(256), 0, st, desc, list, ws, state);
-    hipLaunchKernelGGL(nz_accum_kernel, dim3(bx_site, nlist), dim3(256), 0, st, desc, list, ws, state);
+    const uint32_t slots8 = static_cast<uint32_t>((nlist + 7) / 8) * 8u;
+    hipLaunchKernelGGL(nz_hook_kernel, dim3(static_cast<uint32_t>(bx_hook) * slots8), dim3(256), 0, st, desc, list, nlist,
+                       bx_hook, tabs, ws, state);
+    hipLaunchKernelGGL(nz_compress_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
+                       nlist, bx_site, ws, state);
+    hipLaunchKernelGGL(nz_accum_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list, nlist,
+                       bx_site, ws, state);
     return hipGetLastError();
 }
 

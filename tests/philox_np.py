@@ -36,16 +36,19 @@ def philox4x32_10(c0, c1, c2, c3, k0, k1):
 
 
 def site_keys(seed: int, sample: int, sites, tag: int = 0):
-    """64-bit keys K(i) = (word1 << 32) | word0 for counter (i, lo(sample), hi(sample), tag)
-    under key (lo(seed), hi(seed))."""
+    """64-bit keys of sites i: the Philox block of counter (i // 2, lo(sample),
+    hi(sample), tag) under key (lo(seed), hi(seed)) gives K = (word1 << 32) |
+    word0 to even i and (word3 << 32) | word2 to odd i."""
     sites = np.asarray(sites, dtype=np.uint64)
     n = sites.shape
-    o0, o1, _, _ = philox4x32_10(
-        sites,
+    o0, o1, o2, o3 = philox4x32_10(
+        sites >> np.uint64(1),
         np.full(n, sample & 0xFFFFFFFF, dtype=np.uint64),
         np.full(n, (sample >> 32) & 0xFFFFFFFF, dtype=np.uint64),
         np.full(n, tag, dtype=np.uint64),
         seed & 0xFFFFFFFF,
         (seed >> 32) & 0xFFFFFFFF,
     )
-    return (o1.astype(np.uint64) << np.uint64(32)) | o0.astype(np.uint64)
+    even = (o1.astype(np.uint64) << np.uint64(32)) | o0.astype(np.uint64)
+    odd = (o3.astype(np.uint64) << np.uint64(32)) | o2.astype(np.uint64)
+    return np.where((sites & np.uint64(1)) == 0, even, odd)

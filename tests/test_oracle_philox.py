@@ -32,8 +32,21 @@ def test_site_key_layout(nzo, seed, sample):
     assert nzo.key(seed, sample, 5, 1) != nzo.key(seed, sample, 5, 0)
 
 
+def test_site_pair_shares_one_block(nzo):
+    """Sites 2j and 2j+1 take words (1, 0) and (3, 2) of the block of counter j."""
+    for seed, sample, j in ((3, 4, 0), (2**63 + 5, 2**33 + 1, 12345), (7, 0, 2**27 - 1)):
+        w = philox_np.philox4x32_10(j, sample & 0xFFFFFFFF, sample >> 32, 0, seed & 0xFFFFFFFF, seed >> 32)
+        w = [int(x) for x in w]
+        assert nzo.key(seed, sample, 2 * j) == (w[1] << 32) | w[0]
+        assert nzo.key(seed, sample, 2 * j + 1) == (w[3] << 32) | w[2]
+
+
 def test_keys_uniform_chi2():
     k = philox_np.site_keys(1234, 0, np.arange(1 << 18, dtype=np.uint64))
+    # even and odd sites (different words of the blocks) are each uniform
+    for part in (k, k[0::2], k[1::2]):
+        b = (part >> np.uint64(60)).astype(np.int64)
+        assert stats.chisquare(np.bincount(b, minlength=16)).pvalue > 1e-4
     for shift in (60, 32, 0):
         b = ((k >> np.uint64(shift)) & np.uint64(15)).astype(np.int64)
         cnt = np.bincount(b, minlength=16)
