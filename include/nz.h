@@ -92,10 +92,11 @@ int nz_canonical(const uint64_t *hist, int64_t hist_len, const double *p_grid, i
  *             floor(n0 / N * 2^64) is occupied at once and its clusters are
  *             labelled by parallel connected components; the sequential sweep
  *             continues from there.  If that bulk state already spans, the
- *             sample backs off to n0 - backoff, then to successive halves of
- *             that, then to 0 (below 64 sites), and is redone, so n* and mass
- *             never depend on n0.
- *   backoff   sites to back off by on the first span at n0 (0: halve at once).
+ *             sample backs off to n0 - backoff, then n0 - 3 backoff,
+ *             n0 - 7 backoff, ... (the step doubling each time), then to 0
+ *             (plain sweep), and is redone, so n* and mass never depend on n0.
+ *   backoff   sites to back off by on the first span at n0 (0: halve n0 on
+ *             every span, down to 0 below 64 sites).
  *   band_hi   expected upper bound on n* used to size the key band (sites;
  *             0: library default).  Never changes results, only work.
  *   prio      relative expected cost of a sample, for longest-first

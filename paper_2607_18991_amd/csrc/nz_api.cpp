@@ -545,7 +545,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                     ++g_stats[3];
                     if (h_backoffs) ++h_backoffs[p.job];
                     p.n0 = s.n0b;
-                    p.backoff = 0;
+                    p.backoff *= 2;   // the next backoff, if any, doubles the step
                     desc[di].T0 = s.T0b;
                     desc[di].nb = s.nbb;
                     max_nb = std::max(max_nb, s.nbb);
@@ -611,6 +611,14 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 }
                 g_ms[5] += 1.0;
             }
+            if (getenv("NZ_DEBUG_TRACE")) {
+                int cnt[8] = {0};
+                for (int32_t di = 0; di < n; ++di) ++cnt[std::max(0, std::min(7, static_cast<int>(state[di].status)))];
+                std::fprintf(stderr, "nz: round %d chunk of %d: done %d band %d bucket %d backoff %d prefix %d other %d\n",
+                             rounds, n, cnt[NZ_ST_DONE], cnt[NZ_ST_BAND], cnt[NZ_ST_BUCKET], cnt[NZ_ST_BACKOFF],
+                             cnt[NZ_ST_PREFIX], n - cnt[NZ_ST_DONE] - cnt[NZ_ST_BAND] - cnt[NZ_ST_BUCKET] -
+                                                    cnt[NZ_ST_BACKOFF] - cnt[NZ_ST_PREFIX]);
+            }
             for (int32_t di = 0; di < n; ++di) {
                 Plan p = chunk[chunk_of_desc[di]];
                 const int64_t N = pow5(p.L);
@@ -630,14 +638,20 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 case NZ_ST_BACKOFF:
                     ++g_stats[3];
                     if (h_backoffs) ++h_backoffs[p.job];
-                    // first back off by the caller's step, then halve: a badly
-                    // predicted lattice needs only a few rounds, and n0 reaches 0
-                    // after at most log2(N) of them
-                    if (p.backoff > 0 && p.n0 - p.backoff > 0) {
-                        p.n0 -= p.backoff;
-                        p.backoff = 0;
+                    // back off by the caller's step, doubling it each time
+                    // (n0 - b, n0 - 3b, n0 - 7b, ...), until the start would
+                    // reach 0; without a step, halve.  A badly predicted lattice
+                    // needs only a few rounds, and n0 reaches 0 after at most
+                    // log2(N) of them.
+                    if (p.backoff > 0) {
+                        if (p.n0 - p.backoff > 0) {
+                            p.n0 -= p.backoff;
+                            p.backoff *= 2;
+                        } else {
+                            p.n0 = 0;
+                            p.backoff = 0;
+                        }
                     } else {
-                        p.backoff = 0;
                         p.n0 = p.n0 >= 64 ? p.n0 / 2 : 0;
                     }
                     break;
@@ -669,6 +683,7 @@ size_t batch_bytes(const nz_job *jobs, int32_t njobs, const Tune &tune)
         p.L = jobs[j].L;
         p.mask = jobs[j].zone_mask;
         p.n0 = jobs[j].n0 > 0 ? jobs[j].n0 : 0;
+        p.backoff = jobs[j].backoff;   // sizes the band of a first backoff too
         const int64_t N = pow5(p.L);
         p.band_hi = jobs[j].band_hi > 0 ? std::min<int64_t>(jobs[j].band_hi, N) : default_band_hi(p.L, p.mask, p.n0);
         if (p.band_hi <= p.n0) p.band_hi = std::min<int64_t>(N, p.n0 + 4096);

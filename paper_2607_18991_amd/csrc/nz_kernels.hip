@@ -8,10 +8,11 @@
 //                      (bitset word per 32 sites, parent = self, site list);
 //                      sites in the key band [T0, T0 + nb << shift) are appended
 //                      to the bucket of their key;
-//   nz_hook/compress/  bulk connected components of the prefilled sites
-//   accum kernels      (hook-and-compress with CAS links, then cluster sizes and
-//                      border flags into the root word); a state that already
-//                      spans is flagged for backoff;
+//   nz_hook/label      bulk connected components of the prefilled sites
+//   kernels            (hooking with CAS links, then every member points at its
+//                      root and adds its size and border flags to the root
+//                      word); a state that already spans is flagged for
+//                      backoff;
 //   nz_sort_kernel     each bucket sorted by (key, site) in LDS (bitonic);
 //                      concatenated buckets are exactly the occupation order;
 //   nz_sweep_kernel    persistent: every wave pops a sample (longest first) and
@@ -88,16 +89,14 @@ __device__ __forceinline__ uint32_t allowed_axis(int32_t x, int32_t L)
     return hi >= lo ? ((2u << hi) - (1u << lo)) : 0u;
 }
 
-// Relaxed atomics: wavefront scope for state private to one wave, agent scope
-// for state shared by all workgroups (bulk connected components).
+// Relaxed wavefront-scope accesses: ordinary cached loads and stores that the
+// compiler neither merges nor elides.  They serve state private to one wave and
+// the cache-tolerant walks of the bulk connected components; links and counts
+// shared by all workgroups use agent-scope atomics.
 template <typename T>
 __device__ __forceinline__ T ld_w(T *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT); }
 template <typename T>
 __device__ __forceinline__ void st_w(T *p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT); }
-template <typename T>
-__device__ __forceinline__ T ld_a(T *p) { return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
-template <typename T>
-__device__ __forceinline__ void st_a(T *p, T v) { __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT); }
 
 __device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
 
@@ -384,18 +383,21 @@ __global__ __launch_bounds__(SORT_THREADS) void nz_sort_kernel(const NzSample *_
 }
 
 // ---------------------------------------------------------------------------
-// Bulk connected components of the prefilled sites (hook and compress).
+// Bulk connected components of the prefilled sites (hook, then label).
 // During this phase par[i] is a plain parent index and a root points to
-// itself; every access is an agent-scope atomic because all workgroups work on
-// the same forest at once.  Links always go from the larger root index to the
-// smaller, so a CAS that finds its root unchanged can never form a cycle.
+// itself.  Every link goes from a larger index to a smaller one, and only an
+// agent-scope CAS that finds par[u] == u links u, so along every path indices
+// decrease and no cycle can form.  The walks therefore read through the caches
+// (wavefront-scope accesses): a stale entry is still an ancestor (or a former
+// root), which can only make a CAS fail and retry from the value it returns,
+// one true step further up; path-halving writes store an ancestor.
 
 __device__ __forceinline__ int32_t cc_find(int32_t *par, int32_t x)
 {
-    int32_t p = ld_a(&par[x]);
+    int32_t p = ld_w(&par[x]);
     while (p != x) {
-        const int32_t g = ld_a(&par[p]);
-        if (g != p) st_a(&par[x], g);   // halving: x skips to its grandparent
+        const int32_t g = ld_w(&par[p]);
+        if (g != p) st_w(&par[x], g);   // halving: x skips to its grandparent
         x = p;
         p = g;
     }
@@ -441,6 +443,7 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
         const uint32_t A = allowed_axis(pc & 63, L) | (allowed_axis((pc >> 6) & 63, L) << 5) |
                            (allowed_axis((pc >> 12) & 63, L) << 10) | (allowed_axis((pc >> 18) & 63, L) << 15) |
                            (allowed_axis(pc >> 24, L) << 20);
+        int32_t u = -1;   // the site's root (or an ancestor of it), found at the first edge
         for (int32_t k0 = 0; k0 < zh; k0 += HOOK_UNROLL) {
             int32_t t[HOOK_UNROLL];
             uint32_t w[HOOK_UNROLL];
@@ -456,20 +459,19 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
 #pragma unroll
             for (int q = 0; q < HOOK_UNROLL; ++q) {
                 if (!((w[q] >> (t[q] & 31)) & 1u)) continue;
-                int32_t u = cc_find(par, s);
+                if (u < 0) u = cc_find(par, s);
                 int32_t v = cc_find(par, t[q]);
                 while (u != v) {
-                    if (u < v) {
-                        const int32_t tmp = u;
-                        u = v;
-                        v = tmp;
-                    }
-                    int32_t expected = u;
-                    if (__hip_atomic_compare_exchange_strong(&par[u], &expected, v, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT))
+                    const int32_t hi = max(u, v), lo = min(u, v);
+                    int32_t expected = hi;
+                    if (__hip_atomic_compare_exchange_strong(&par[hi], &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                             __HIP_MEMORY_SCOPE_AGENT)) {
+                        u = lo;   // the site's root is now lo
                         break;
-                    u = cc_find(par, expected);
-                    v = cc_find(par, v);
+                    }
+                    // hi is no longer a root: go on from the parent the CAS returned
+                    u = cc_find(par, u == hi ? expected : u);
+                    v = cc_find(par, v == hi ? expected : v);
                 }
             }
         }
@@ -504,17 +506,17 @@ __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__rest
     for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
         const int32_t s = static_cast<int32_t>(prefix[k]);
         int32_t r = s;
-        int32_t p = ld_a(&par[r]);
+        int32_t p = ld_w(&par[r]);
         while (p >= 0 && p != r) {
             r = p;
-            p = ld_a(&par[r]);
+            p = ld_w(&par[r]);
         }
         if (r == s) {
             const uint32_t fl = border_flags(static_cast<uint32_t>(s), L, d.magic);
-            st_a(&par[s], static_cast<int32_t>(NZ_ROOT | fl | 1u));
+            st_w(&par[s], static_cast<int32_t>(NZ_ROOT | fl | 1u));
             if (fl == NZ_FLAGS) state[sid].status = NZ_ST_BACKOFF;   // L = 1: one site spans
         } else {
-            st_a(&par[s], r);
+            st_w(&par[s], r);
         }
     }
 }

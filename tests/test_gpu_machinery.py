@@ -130,6 +130,17 @@ def test_block_matches_single_site(L):
     assert (a[0] > 0).all()
 
 
+def test_sized_workspace_holds_prefilled_batch_in_one_chunk():
+    """The workspace size reported for jobs with a prefill and a backoff step
+    also holds the backed-off key band, so the batch needs no second chunk."""
+    jobs = [dict(L=8, zone_mask=m, seed=61, nsamples=40, n0=n0, backoff=bo, band_hi=8**5)
+            for m, n0, bo in ((1, 1000, 500), (0x07, 150, 60), (0x7F, 15, 10))]
+    gn, gm, _, stats = run_batch(jobs)
+    assert_same(jobs, gn, gm, *oracle_batch(jobs))
+    assert stats["backoffs"] == 0 and stats["band_redo"] == 0 and stats["bucket_redo"] == 0
+    assert stats["chunks"] == 1
+
+
 def test_small_workspace_chunks():
     from paper_2607_18991_amd import nz
 
