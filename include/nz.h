@@ -120,7 +120,7 @@ typedef struct {
  * Tuning knobs (all 0 = automatic).  None of them changes any output.
  *   residency       1: occupancy bitset in LDS (L^5 / 8 bytes must fit);
  *                   2: everything in HBM; 3: bitset and parents in LDS.
- *   wg_waves        waves per workgroup of the sweep (1..16).
+ *   wg_waves        waves per workgroup of the sweep (1..4).
  *   waves_per_simd  resident sweep waves per SIMD of the persistent launch.
  *   bucket_log2     log2 of the mean number of keys per sort bucket (4..10).
  *   sweep_mode      1: one site per wave step (z lanes check the neighbours);

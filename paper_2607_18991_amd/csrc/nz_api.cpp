@@ -299,7 +299,7 @@ int read_tune(const nz_tuning *t, Tune &out)
     out = Tune{};
     if (!t) return NZ_OK;
     if (t->residency < 0 || t->residency > 3) return fail(NZ_EINVAL, "tuning: residency %d outside [0, 3]", t->residency);
-    if (t->wg_waves < 0 || t->wg_waves > 16) return fail(NZ_EINVAL, "tuning: wg_waves %d outside [0, 16]", t->wg_waves);
+    if (t->wg_waves < 0 || t->wg_waves > 4) return fail(NZ_EINVAL, "tuning: wg_waves %d outside [0, 4]", t->wg_waves);
     if (t->waves_per_simd < 0 || t->waves_per_simd > 8)
         return fail(NZ_EINVAL, "tuning: waves_per_simd %d outside [0, 8]", t->waves_per_simd);
     if (t->bucket_log2 != 0 && (t->bucket_log2 < 4 || t->bucket_log2 > 10))

@@ -823,20 +823,24 @@ __device__ __forceinline__ void sweep_step(const SweepMem<RES> &m, uint32_t *lds
 // appears, and blocks that do not fit the tables below, are undone and redone
 // one site at a time, which yields the exact n* and mass.
 //
+// While a block is processed its sites are marked occupied and their parent
+// entries hold BLK_MARK | position, a value no parent index reaches (N < 2^29)
+// and no root word has (bit 31 clear).  An occupied neighbour whose parent
+// entry carries the mark is a site of the block, earlier or later in the order.
+//
 // Per-wave LDS slice (32-bit words, at the end of the wave's slice):
-//   bkey[256] bpos[256]  open-addressing table: block site -> position
-//   rkey[256]            open-addressing table of the earlier roots touched
-//   npar[320]            node parents: node i < 64 is position i, node 64 + h
-//                        the earlier root in rkey slot h
-//   nword[320]           node words in the root-word format (size, flags)
+//   rkey[256]    open-addressing table of the earlier roots the block touches
+//   npar[320]    node parents: node i < 64 is position i, node 64 + h the
+//                earlier root in rkey slot h
+//   nword[320]   node words in the root-word format (size, flags)
 
-constexpr int BLK_K = 8;               // occupied earlier neighbours recorded per site
-constexpr uint32_t BLK_BSLOTS = 256;
+constexpr int BLK_K = 8;               // occupied neighbours recorded per site
 constexpr uint32_t BLK_RSLOTS = 256;
 constexpr uint32_t BLK_NODES = 64 + BLK_RSLOTS;
 constexpr uint32_t BLK_EMPTY = 0xFFFFFFFFu;
-constexpr uint32_t BLK_LDS_WORDS = 2 * BLK_BSLOTS + BLK_RSLOTS + 2 * BLK_NODES;
+constexpr uint32_t BLK_LDS_WORDS = BLK_RSLOTS + 2 * BLK_NODES;
 constexpr int BLK_CHUNK = 16;          // neighbour offsets whose loads are issued together
+constexpr int32_t BLK_MARK = 0x40000000;
 
 __device__ __forceinline__ uint32_t blk_hash(uint32_t t) { return (t * 0x9E3779B1u) >> 24; }
 
@@ -855,16 +859,41 @@ __device__ __forceinline__ uint32_t blk_find(uint32_t *npar, uint32_t x)
     }
 }
 
+// Occupied neighbours among BLK_CHUNK offsets (their loads issued together),
+// appended to nl[0 .. cntn) by site.
+template <int RES>
+__device__ __forceinline__ void blk_scan(const SweepMem<RES> &m, uint32_t *lds, const NzOffset (&oq)[BLK_CHUNK],
+                                         bool act, int32_t s, uint32_t A, int32_t (&nl)[BLK_K], int &cntn)
+{
+    int32_t tq[BLK_CHUNK];
+    uint32_t wq[BLK_CHUNK];
+#pragma unroll
+    for (int q = 0; q < BLK_CHUNK; ++q) {
+        const bool ok = act && (oq[q].code & ~A) == 0u;
+        tq[q] = s + oq[q].stride;
+        wq[q] = ok ? m.occ_ld(lds, static_cast<uint32_t>(tq[q]) >> 5) : 0u;
+    }
+#pragma unroll
+    for (int q = 0; q < BLK_CHUNK; ++q) {
+        const bool rec = (wq[q] >> (tq[q] & 31)) & 1u;
+#pragma unroll
+        for (int k = 0; k < BLK_K; ++k) nl[k] = (rec && cntn == k) ? tq[q] : nl[k];
+        cntn += rec ? 1 : 0;
+    }
+}
+
 enum { BLK_COMMITTED = 0, BLK_FALLBACK = 1 };
 
 // Adds the nbk (1..64) sites whose packed coordinates lane i holds in pc (lane
-// i = position i of the order).  BLK_COMMITTED: the block is merged into the
-// union-find and no cluster spans.  BLK_FALLBACK: the occupancy bits of the
-// block are cleared again and parents are as before (up to path halving); the
-// caller adds the sites one at a time.
+// i = position i of the order); off0 holds the first BLK_CHUNK offsets of the
+// table.  BLK_COMMITTED: the block is merged into the union-find and no cluster
+// spans.  BLK_FALLBACK: the occupancy bits of the block are cleared again and
+// the parents of earlier sites are as before (up to path halving); the caller
+// adds the sites one at a time.
 template <int RES>
 __device__ __forceinline__ int block_step(const SweepMem<RES> &m, uint32_t *lds, uint32_t hbase, int nbk, uint32_t pc,
-                                          int32_t L, const NzOffset *tab, int32_t z, int max_old)
+                                          int32_t L, const NzOffset *tab, const NzOffset (&off0)[BLK_CHUNK], int32_t z,
+                                          int max_old)
 {
     const uint32_t lane = lane_id();
     const bool act = static_cast<int>(lane) < nbk;
@@ -873,90 +902,56 @@ __device__ __forceinline__ int block_step(const SweepMem<RES> &m, uint32_t *lds,
     const uint32_t A = allowed_axis(x0, L) | (allowed_axis(x1, L) << 5) | (allowed_axis(x2, L) << 10) |
                        (allowed_axis(x3, L) << 15) | (allowed_axis(x4, L) << 20);
     const uint32_t fl = (x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u);
-    uint32_t *bkey = lds + hbase;
-    uint32_t *bpos = bkey + BLK_BSLOTS;
-    uint32_t *rkey = bpos + BLK_BSLOTS;
+    uint32_t *rkey = lds + hbase;
     uint32_t *npar = rkey + BLK_RSLOTS;
     uint32_t *nword = npar + BLK_NODES;
 
-    // 1. clear the tables, enter the block's sites, mark them occupied
-#pragma unroll
-    for (uint32_t w = 0; w < BLK_BSLOTS; w += 64) st_w(&bkey[w + lane], BLK_EMPTY);
+    // 1. mark the block's sites (occupied, parent = mark | position); clear
+    //    the tables
+    if (act) {
+        m.par_st(lds, s, BLK_MARK | static_cast<int32_t>(lane));
+        m.occ_or(lds, static_cast<uint32_t>(s) >> 5, 1u << (s & 31));
+    }
 #pragma unroll
     for (uint32_t w = 0; w < BLK_RSLOTS; w += 64) st_w(&rkey[w + lane], BLK_EMPTY);
     for (uint32_t n = lane; n < BLK_NODES; n += 64) st_w(&npar[n], n);
     st_w(&nword[lane], act ? (NZ_ROOT | fl | 1u) : 0u);
-    __builtin_amdgcn_wave_barrier();
-    if (act) {
-        uint32_t h = blk_hash(static_cast<uint32_t>(s));
-        for (;;) {   // at most 64 keys in 256 slots: an empty slot is always found
-            uint32_t expected = BLK_EMPTY;
-            if (__hip_atomic_compare_exchange_strong(&bkey[h], &expected, static_cast<uint32_t>(s), __ATOMIC_RELAXED,
-                                                     __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT)) {
-                st_w(&bpos[h], lane);
-                break;
-            }
-            h = (h + 1) & (BLK_BSLOTS - 1);
-        }
-        m.occ_or(lds, static_cast<uint32_t>(s) >> 5, 1u << (s & 31));
-    }
-    __builtin_amdgcn_wave_barrier();
 
-    // 2. occupied neighbours that precede the site: sites of earlier blocks
-    //    (recorded as the site) and earlier positions of this block (recorded
-    //    as -(position + 1)); later positions of the block are skipped
+    // 2. occupied neighbours (sites of earlier blocks and of this block)
     int32_t nl[BLK_K];
 #pragma unroll
     for (int k = 0; k < BLK_K; ++k) nl[k] = 0;
     int cntn = 0;
-    for (int c0 = 0; c0 < z; c0 += BLK_CHUNK) {
-        int32_t tq[BLK_CHUNK];
-        uint32_t wq[BLK_CHUNK];
+    blk_scan<RES>(m, lds, off0, act, s, A, nl, cntn);
+    for (int c0 = BLK_CHUNK; c0 < z; c0 += BLK_CHUNK) {
+        NzOffset oq[BLK_CHUNK];
 #pragma unroll
         for (int q = 0; q < BLK_CHUNK; ++q) {
-            NzOffset o;
-            o.stride = 0;
-            o.code = 0xFFFFFFFFu;
-            if (c0 + q < z) o = tab[c0 + q];
-            const bool ok = act && (o.code & ~A) == 0u;
-            tq[q] = s + o.stride;
-            wq[q] = ok ? m.occ_ld(lds, static_cast<uint32_t>(tq[q]) >> 5) : 0u;
+            oq[q].stride = 0;
+            oq[q].code = 0xFFFFFFFFu;
+            if (c0 + q < z) oq[q] = tab[c0 + q];
         }
-#pragma unroll
-        for (int q = 0; q < BLK_CHUNK; ++q) {
-            const uint32_t t = static_cast<uint32_t>(tq[q]);
-            if ((wq[q] >> (t & 31)) & 1u) {
-                int j = -1;
-                uint32_t h = blk_hash(t);
-                for (;;) {
-                    const uint32_t key = ld_w(&bkey[h]);
-                    if (key == t) {
-                        j = static_cast<int>(ld_w(&bpos[h]));
-                        break;
-                    }
-                    if (key == BLK_EMPTY) break;
-                    h = (h + 1) & (BLK_BSLOTS - 1);
-                }
-                const bool rec = j < static_cast<int>(lane);
-                const int32_t val = j < 0 ? tq[q] : -(j + 1);
-#pragma unroll
-                for (int k = 0; k < BLK_K; ++k) nl[k] = (rec && cntn == k) ? val : nl[k];
-                cntn += rec ? 1 : 0;
-            }
-        }
+        blk_scan<RES>(m, lds, oq, act, s, A, nl, cntn);
     }
     bool bad = cntn > BLK_K;
+    __builtin_amdgcn_wave_barrier();
 
-    // 3. roots of the earlier sites (first parent loads issued together), each
-    //    entered once into the root table; nl[k] becomes the neighbour's node
+    // 3. parent words of the recorded neighbours (loads issued together).  A
+    //    mark names a position of this block: an earlier one becomes an edge to
+    //    that node, a later one is dropped.  Otherwise the neighbour's root is
+    //    found and entered once into the root table; nl[k] becomes the node
+    //    (-1: no edge).
     int32_t pv[BLK_K];
 #pragma unroll
-    for (int k = 0; k < BLK_K; ++k) pv[k] = (!bad && k < cntn && nl[k] >= 0) ? m.par_ld(lds, nl[k]) : -1;
+    for (int k = 0; k < BLK_K; ++k) pv[k] = (!bad && k < cntn) ? m.par_ld(lds, nl[k]) : -1;
     int nnew = 0;
 #pragma unroll
     for (int k = 0; k < BLK_K; ++k) {
         if (!bad && k < cntn) {
-            if (nl[k] >= 0) {
+            if (pv[k] >= BLK_MARK) {
+                const int j = pv[k] & 63;
+                nl[k] = j < static_cast<int>(lane) ? j : -1;
+            } else {
                 int32_t root;
                 uint32_t word;
                 sweep_find_from<RES>(m, lds, nl[k], pv[k], root, word);
@@ -980,8 +975,6 @@ __device__ __forceinline__ int block_step(const SweepMem<RES> &m, uint32_t *lds,
                 }
                 bad = bad || slot < 0;
                 nl[k] = 64 + slot;
-            } else {
-                nl[k] = -nl[k] - 1;
             }
         }
     }
@@ -1001,7 +994,7 @@ __device__ __forceinline__ int block_step(const SweepMem<RES> &m, uint32_t *lds,
         bool hooked = false;
 #pragma unroll
         for (int k = 0; k < BLK_K; ++k) {
-            if (k < cntn) {
+            if (k < cntn && nl[k] >= 0) {
                 const uint32_t a = blk_find(npar, lane);
                 const uint32_t b = blk_find(npar, static_cast<uint32_t>(nl[k]));
                 if (a != b) {
@@ -1069,7 +1062,7 @@ struct SweepOut {
 };
 
 template <int NCH, int RES, bool BLOCK>
-__global__ void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
+__global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
 {
     extern __shared__ uint32_t lds[];
     __shared__ int32_t claim[16];   // per-wave work claim
@@ -1113,20 +1106,23 @@ __global__ void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
         }
 
         const NzOffset *tab = a.tabs + d.tab;
+        // offset c * 64 + lane of the table per lane, for one-site-at-a-time steps
         int32_t ostride[NCH];
         uint32_t ocode[NCH];
+        auto load_offsets = [&]() {
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const int32_t j = c * 64 + static_cast<int32_t>(lane);
-            if (j < z) {
-                const NzOffset o = tab[j];
-                ostride[c] = o.stride;
-                ocode[c] = o.code;
-            } else {
-                ostride[c] = 0;
-                ocode[c] = 0xFFFFFFFFu;   // never inside: bits above 25 are never allowed
+            for (int c = 0; c < NCH; ++c) {
+                const int32_t j = c * 64 + static_cast<int32_t>(lane);
+                if (j < z) {
+                    const NzOffset o = tab[j];
+                    ostride[c] = o.stride;
+                    ocode[c] = o.code;
+                } else {
+                    ostride[c] = 0;
+                    ocode[c] = 0xFFFFFFFFu;   // never inside: bits above 25 are never allowed
+                }
             }
-        }
+        };
 
         int32_t r = a.state[sid].n0;   // sites already occupied
         int32_t status = NZ_ST_BAND;
@@ -1137,6 +1133,13 @@ __global__ void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
             const uint32_t *counts = reinterpret_cast<const uint32_t *>(a.ws + d.off_counts);
             const uint32_t *sites = reinterpret_cast<const uint32_t *>(a.ws + d.off_sites);
             const uint32_t hbase = m.lbase + a.lds_words - BLK_LDS_WORDS;
+            NzOffset off0[BLK_CHUNK];   // the first offsets, kept for the whole sample
+#pragma unroll
+            for (int q = 0; q < BLK_CHUNK; ++q) {
+                off0[q].stride = 0;
+                off0[q].code = 0xFFFFFFFFu;
+                if (q < z) off0[q] = tab[q];
+            }
             SiteStep<NCH> cur;
             bool done = false;
             for (int32_t b = 0; b < nb && !done; ++b) {
@@ -1149,8 +1152,9 @@ __global__ void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
                 for (uint32_t j0 = 0; j0 < cnt; j0 += 64) {
                     const int nbk = static_cast<int>(min(64u, cnt - j0));
                     const uint32_t pcl = static_cast<int>(lane) < nbk ? bs[j0 + lane] : 0u;
-                    const int res = block_step<RES>(m, lds, hbase, nbk, pcl, L, tab, z, a.blk_old);
+                    const int res = block_step<RES>(m, lds, hbase, nbk, pcl, L, tab, off0, z, a.blk_old);
                     if (res == BLK_FALLBACK) {
+                        load_offsets();
                         for (int i = 0; i < nbk; ++i) {
                             ++r;
                             cur.prepare(m, lds, bcast(pcl, i), L, ostride, ocode);
@@ -1171,6 +1175,7 @@ __global__ void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
                 }
             }
         } else {
+        load_offsets();
         // The band in (key, site) order; the occupancy words of the next site are
         // loaded while the current one is processed.  Only the current site can
         // change them in between, so they are patched with its bit afterwards.

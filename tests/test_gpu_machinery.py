@@ -86,7 +86,7 @@ def test_prefix_list_redo():
 
 @pytest.mark.parametrize("tune", [
     dict(residency=1), dict(residency=3), dict(residency=2, wg_waves=1), dict(wg_waves=2, waves_per_simd=2),
-    dict(wg_waves=8), dict(bucket_log2=4), dict(bucket_log2=10), dict(residency=1, wg_waves=2),
+    dict(wg_waves=3), dict(bucket_log2=4), dict(bucket_log2=10), dict(residency=1, wg_waves=2),
     dict(sweep_mode=1), dict(sweep_mode=2), dict(sweep_mode=1, residency=1), dict(sweep_mode=1, residency=3),
     dict(sweep_mode=2, residency=3), dict(sweep_mode=2, residency=1, wg_waves=4),
 ])
