@@ -30,6 +30,14 @@ SEEDS = {16: 0x5EED1016, 24: 0x5EED1024}
 HBM_PEAK_GBS = 8000.0
 
 
+def random_masks(count=20, seed=0x24):
+    """The non-compact neighbourhoods of the L = 24 table: `count` distinct
+    masks drawn uniformly from the 120 non-compact ones (NumPy, fixed seed)."""
+    pool = [m for m in range(1, 128) if m not in COMPACT]
+    rng = np.random.default_rng(seed)
+    return sorted(int(m) for m in rng.choice(pool, size=count, replace=False))
+
+
 def bytes_per_addition(z: int) -> float:
     """Algorithmic HBM bytes of one sequential site addition: the site (4 B), z
     occupancy bits and its own word (z/8 + 4), its parent entry (4), about two
@@ -38,20 +46,20 @@ def bytes_per_addition(z: int) -> float:
     return 22.0 + z / 8.0
 
 
-def base_jobs(L, samples):
-    return [dict(L=L, zone_mask=m, seed=SEEDS.get(L, 0x5EED0000 + L), nsamples=samples) for m in COMPACT]
+def base_jobs(L, samples, masks=COMPACT):
+    return [dict(L=L, zone_mask=m, seed=SEEDS.get(L, 0x5EED0000 + L), nsamples=samples) for m in masks]
 
 
-def run_mode(nz, torch, make_jobs, steps, warmup):
+def run_mode(nz, torch, make_jobs, steps, warmup, tune):
     """make_jobs() is called inside every step (it runs the MLP in learned mode)."""
     jobs = make_jobs()
     total = sum(j["nsamples"] for j in jobs)
-    ws_bytes = nz.nz_batch_workspace_bytes(jobs)
+    ws_bytes = nz.nz_batch_workspace_bytes(jobs, tune)
     ws = torch.empty(ws_bytes, dtype=torch.uint8, device="cuda")
     dn = torch.zeros(total, dtype=torch.int32, device="cuda")
     dm = torch.zeros(total, dtype=torch.int32, device="cuda")
     for _ in range(warmup):
-        nz.nz_sweep_batch(make_jobs(), ws, dn, dm)
+        nz.nz_sweep_batch(make_jobs(), ws, dn, dm, tune=tune)
     torch.cuda.synchronize()
     nz.nz_set_timing(True)
     phase = {"keys_ms": 0.0, "cc_ms": 0.0, "sort_ms": 0.0, "sweep_ms": 0.0, "total_ms": 0.0, "sweep_launches": 0}
@@ -59,7 +67,7 @@ def run_mode(nz, torch, make_jobs, steps, warmup):
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
-        nz.nz_sweep_batch(make_jobs(), ws, dn, dm)
+        nz.nz_sweep_batch(make_jobs(), ws, dn, dm, tune=tune)
         t = nz.nz_last_batch_timing()
         for k in phase:
             phase[k] += t[k]
@@ -70,7 +78,7 @@ def run_mode(nz, torch, make_jobs, steps, warmup):
     nz.nz_set_timing(False)
     del ws
     return {"wall": wall, "ns": dn.cpu().numpy(), "ms": dm.cpu().numpy(), "phase": phase, "stats": stats,
-            "jobs": jobs}
+            "jobs": jobs, "tune": tune}
 
 
 def summarise(res, steps, S, z):
@@ -79,9 +87,10 @@ def summarise(res, steps, S, z):
     serial = res["stats"]["serial_steps"] / steps
     alg_bytes = 0.0
     # serial steps per mask are not reported separately; weight by each mask's share of n*
-    share = np.array([res["ns"][k * S:(k + 1) * S].astype(np.float64).sum() for k in range(len(COMPACT))])
+    masks = [j["zone_mask"] for j in res["jobs"]]
+    share = np.array([res["ns"][k * S:(k + 1) * S].astype(np.float64).sum() for k in range(len(masks))])
     share = share / share.sum()
-    for k, m in enumerate(COMPACT):
+    for k, m in enumerate(masks):
         alg_bytes += serial * share[k] * bytes_per_addition(z[m])
     launches = max(res["phase"]["sweep_launches"], 1)
     sweep_ms = res["phase"]["sweep_ms"] / launches
@@ -95,6 +104,7 @@ def summarise(res, steps, S, z):
         "phase_ms_per_step": {k: v / steps for k, v in res["phase"].items() if k != "sweep_launches"},
         "sweep_kernel_ms": sweep_ms,
         "sweep_alg_bytes": alg_bytes,
+        "tuning": res["tune"],
     }
 
 
@@ -124,6 +134,9 @@ def main():
     ap.add_argument("--l24-samples", type=int, default=200, help="samples per mask of the L=24 table (0: skip)")
     ap.add_argument("--mode", choices=["both", "learned", "plain"], default="both",
                     help="profiling aid: run only one path (the JSON line then reports that path)")
+    ap.add_argument("--autotune-out", default=None,
+                    help="tune the benchmark's batches as a whole, add them to the tuning table and write it "
+                         "to this path (no benchmark is run)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(json.dumps({"error": "this build measures one GPU; samples are independent and shard by sample "
@@ -134,17 +147,39 @@ def main():
 
     from paper_2607_18991_amd import learned, nz
 
+    from paper_2607_18991_amd import autotune
+
     torch.cuda.set_device(0)
     L, S = args.L, args.samples
     N = L**5
     model = learned.PrefillModel.load()
     jobs0 = base_jobs(L, S)
-    z = {m: nz.nz_coordination(m) for m in COMPACT}
+    masks24 = COMPACT + random_masks()
+    z = {m: nz.nz_coordination(m) for m in range(1, 128)}
+
+    if args.autotune_out:
+        table = autotune.load_table()
+        batches = [(f"L={L} x 7 compact x {S}, plain", learned.plan_band_only(model, jobs0)),
+                   (f"L={L} x 7 compact x {S}, learned", model.plan(jobs0))]
+        if args.l24_samples > 0:
+            j24 = base_jobs(24, args.l24_samples, masks24)
+            batches += [(f"L=24 x 27 masks x {args.l24_samples}, plain", learned.plan_band_only(model, j24)),
+                        (f"L=24 x 27 masks x {args.l24_samples}, learned", model.plan(j24))]
+        for name, jobs in batches:
+            e = autotune.tune_batch(jobs, log=lambda m: print(f"{name}: {m}", flush=True))
+            autotune.add_batch(table, jobs, e, name)
+            print(f"{name}: best {e['tune']} {e['ms']} ms (default {e['default_ms']} ms)", flush=True)
+        autotune.save_table(table, args.autotune_out)
+        return
 
     if args.mode in ("both", "plain"):
-        plain = run_mode(nz, torch, lambda: learned.plan_band_only(model, jobs0), args.steps, args.warmup)
+        jp = learned.plan_band_only(model, jobs0)
+        plain = run_mode(nz, torch, lambda: learned.plan_band_only(model, jobs0), args.steps, args.warmup,
+                         autotune.for_jobs(jp) or None)
     if args.mode in ("both", "learned"):
-        learn = run_mode(nz, torch, lambda: model.plan(jobs0), args.steps, args.warmup)
+        jl = model.plan(jobs0)
+        learn = run_mode(nz, torch, lambda: model.plan(jobs0), args.steps, args.warmup,
+                         autotune.for_jobs(jl) or None)
     if args.mode == "plain":
         learn = plain
     elif args.mode == "learned":
@@ -181,18 +216,20 @@ def main():
                      "kernel_ms": kernel_ms},
     }
     if args.l24_samples > 0:
-        # the same comparison at L = 24 (7,962,624 sites), one timed step per mode
-        j24 = base_jobs(24, args.l24_samples)
-        p24 = run_mode(nz, torch, lambda: learned.plan_band_only(model, j24), 1, 0)
-        l24 = run_mode(nz, torch, lambda: model.plan(j24), 1, 0)
+        # the same comparison at L = 24 (7,962,624 sites): the 7 compact and 20
+        # random neighbourhoods, one timed step per mode
+        j24 = base_jobs(24, args.l24_samples, masks24)
+        jp24, jl24 = learned.plan_band_only(model, j24), model.plan(j24)
+        p24 = run_mode(nz, torch, lambda: learned.plan_band_only(model, j24), 1, 0, autotune.for_jobs(jp24) or None)
+        l24 = run_mode(nz, torch, lambda: model.plan(j24), 1, 0, autotune.for_jobs(jl24) or None)
         s24p, s24l = summarise(p24, 1, args.l24_samples, z), summarise(l24, 1, args.l24_samples, z)
-        out["L24"] = {"samples_per_mask": args.l24_samples,
+        out["L24"] = {"samples_per_mask": args.l24_samples, "masks": masks24,
                       "outputs_identical_plain_vs_learned": bool((p24["ns"] == l24["ns"]).all() and
                                                                  (p24["ms"] == l24["ms"]).all()),
                       "speedup_learned_vs_plain": s24p["ms_per_step"] / s24l["ms_per_step"],
                       "learned": s24l, "plain": s24p}
     if not args.no_cpu:
-        per = 4 if L >= 16 else 32
+        per = 8 if L >= 16 else 32
         cpu_rate, threads, res = cpu_baseline(jobs0, per)
         parity = all((res[m][0] == learn["ns"][k * S:k * S + per]).all() and
                      (res[m][1] == learn["ms"][k * S:k * S + per]).all() for k, m in enumerate(COMPACT))

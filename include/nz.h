@@ -128,7 +128,8 @@ typedef struct {
  *                   unions are merged by a connected-components pass in LDS;
  *                   the block in which spanning first occurs, and a block
  *                   that does not fit the LDS tables, is redone one site at a
- *                   time).
+ *                   time); 0: 64 sites per step for z <= 512, one site per
+ *                   step for wider neighbourhoods.
  */
 typedef struct {
     int32_t residency;

@@ -573,7 +573,12 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             int residency = tune.residency == 3 ? 2 : (tune.residency == 1 ? 1 : 0);
             const uint32_t occ_words = ((max_N + 63) / 64) * 2;
             uint32_t lds_words = residency == 2 ? occ_words + max_N : (residency == 1 ? occ_words : 0);
-            const bool block = tune.sweep_mode != 1;
+            // sweep mode: 2 = 64 sites per step for every sample; auto = 64 sites per
+            // step for z <= 512 (wider neighbourhoods are faster one site at a time)
+            int32_t min_z = 1 << 30;
+            for (const NzSample &d : desc) min_z = std::min(min_z, d.z);
+            const int32_t blk_zmax = tune.sweep_mode == 2 ? 892 : 512;
+            const bool block = tune.sweep_mode == 2 || (tune.sweep_mode == 0 && min_z <= blk_zmax);
             if (block) lds_words += nz::block_lds_words();
             int wg_waves = tune.wg_waves ? tune.wg_waves : (residency ? 1 : 4);
             int wps = tune.waves_per_simd ? tune.waves_per_simd : 8;
@@ -596,6 +601,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             args.lds_words = lds_words;
             args.dcap = tune.dcap;
             args.blk_old = env_blk_old();
+            args.blk_zmax = blk_zmax;
             HIP_TRY(nz::launch_sweep(nch_for(max_z), residency, block, args, d_nstar, d_mass, d_outidx, grid, wg_waves, st));
             if (pe) HIP_TRY(hipEventRecord(pe->ev[4], st));
 

@@ -78,4 +78,5 @@ struct NzSweepArgs {
     uint32_t lds_words;       // 32-bit LDS words per wave (LDS residencies)
     int32_t dcap;             // distinct roots held per step before an early merge (2..64)
     int32_t blk_old;          // block sweep: earlier roots one block may touch (0..256)
+    int32_t blk_zmax;         // block sweep for samples with z <= blk_zmax, one site per step above
 };

@@ -1128,7 +1128,10 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         int32_t status = NZ_ST_BAND;
         int32_t nstar = 0, mass = 0;
 
-        if constexpr (BLOCK) {
+        // 64 sites per step up to the launch's z limit, one site per step above it
+        bool use_block = false;
+        if constexpr (BLOCK) use_block = z <= a.blk_zmax;
+        if (use_block) {
             // 64 sites of the band at a time; blocks do not cross buckets
             const uint32_t *counts = reinterpret_cast<const uint32_t *>(a.ws + d.off_counts);
             const uint32_t *sites = reinterpret_cast<const uint32_t *>(a.ws + d.off_sites);

@@ -1,0 +1,70 @@
+"""Host side of the autotuner: z-classes, candidate shapes the library accepts,
+table lookup and the choice for a mixed batch (not GPU)."""
+import json
+
+import pytest
+
+from paper_2607_18991_amd import autotune, nz
+
+
+def test_zclass_follows_offset_chunks():
+    assert [autotune.zclass(z) for z in (10, 64, 65, 128, 130, 256, 332, 512, 572, 892)] == \
+        [64, 64, 128, 128, 256, 256, 512, 512, 892, 892]
+    for zc, mask in autotune.REPRESENTATIVE.items():
+        assert autotune.zclass(nz.nz_coordination(mask)) == zc
+
+
+@pytest.mark.parametrize("L", [4, 8, 16, 24])
+def test_candidates_are_accepted_by_the_library(L):
+    jobs = [dict(L=L, zone_mask=1, seed=1, nsamples=2)]
+    for cand in autotune.candidates(L):
+        assert nz.nz_batch_workspace_bytes(jobs, cand) > 0
+    # LDS residencies only where the state fits
+    res = {c["residency"] for c in autotune.candidates(L)}
+    assert (1 in res) == (L <= 16) and (3 in res) == (L <= 8)
+
+
+def test_lookup_and_batch_choice(tmp_path):
+    table = {"format": autotune.FORMAT, "entries": {
+        "16:64": {"tune": {"residency": 2, "wg_waves": 4, "waves_per_simd": 8, "sweep_mode": 2}},
+        "16:892": {"tune": {"residency": 1, "wg_waves": 1, "waves_per_simd": 8, "sweep_mode": 1}},
+        "8:64": {"tune": {"residency": 3, "wg_waves": 1, "waves_per_simd": 8, "sweep_mode": 2}}}}
+    p = tmp_path / "t.json"
+    p.write_text(json.dumps(table))
+    t = autotune.load_table(str(p))
+    assert autotune.lookup(16, 0x7F, t)["residency"] == 1
+    assert autotune.lookup(16, 0x01, t)["sweep_mode"] == 2
+    assert autotune.lookup(12, 0x01, t) == {}
+    jobs = [dict(L=8, zone_mask=1, nsamples=10), dict(L=16, zone_mask=0x7F, nsamples=10), dict(L=16, zone_mask=0x01, nsamples=10)]
+    assert autotune.for_jobs(jobs, t) == table["entries"]["16:64"]["tune"]
+    assert autotune.for_jobs([], t) == {}
+
+
+def test_shipped_table_is_valid():
+    t = autotune.load_table()
+    assert t["format"] == autotune.FORMAT
+    for k, e in t["entries"].items():
+        L, zc = (int(x) for x in k.split(":"))
+        assert zc in autotune.ZCLASSES
+        nz.nz_batch_workspace_bytes([dict(L=L, zone_mask=autotune.REPRESENTATIVE[zc], seed=1, nsamples=1)],
+                                    e["tune"] or None)
+        assert e["ms"] <= e["default_ms"] * 1.0001
+
+
+def test_batch_entries_and_lds_guard():
+    table = {"format": autotune.FORMAT, "entries": {
+        "16:64": {"tune": {"residency": 1, "wg_waves": 1, "waves_per_simd": 8, "sweep_mode": 2}}}}
+    few = [dict(L=16, zone_mask=1, seed=1, nsamples=100)]
+    many = [dict(L=16, zone_mask=1, seed=1, nsamples=1000)]
+    assert autotune.for_jobs(few, table)["residency"] == 1
+    assert autotune.for_jobs(many, table)["residency"] == 2
+    autotune.add_batch(table, many, {"tune": {"residency": 2, "wg_waves": 4, "waves_per_simd": 4, "sweep_mode": 1}},
+                       "L16 x 1000")
+    assert autotune.for_jobs(many, table)["wg_waves"] == 4
+    # the signature ignores the planned n0 values but not whether a prefill is used
+    assert autotune.signature([dict(L=16, zone_mask=1, nsamples=10, n0=5)]) == \
+        autotune.signature([dict(L=16, zone_mask=1, nsamples=10, n0=7)])
+    assert autotune.signature([dict(L=16, zone_mask=1, nsamples=10, n0=5)]) != \
+        autotune.signature([dict(L=16, zone_mask=1, nsamples=10)])
+    for c in autotune.batch_candidates():
+        assert nz.nz_batch_workspace_bytes(many, c) > 0

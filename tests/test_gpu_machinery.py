@@ -171,3 +171,23 @@ def test_L24_sampled():
     jobs = [dict(L=24, zone_mask=m, seed=0x5EED5, nsamples=1) for m in (0x7F, 0x1F)]
     gn, gm, _, _ = run_batch(jobs)
     assert_same(jobs, gn, gm, *oracle_batch(jobs))
+
+
+def test_autotune_class_keeps_outputs():
+    """Timing every candidate of a class checks each against the default's
+    outputs (tune_class raises on a difference) and keeps the fastest."""
+    from paper_2607_18991_amd import autotune
+
+    e = autotune.tune_class(5, 64, 16)
+    assert e["ms"] <= e["default_ms"]
+    assert any("ms" in t for t in e["tried"])
+
+
+def test_shipped_tuning_reproduces_oracle():
+    from paper_2607_18991_amd import autotune
+
+    for L in (4, 8):
+        for m in (0x01, 0x04, 0x07, 0x1F, 0x7F):
+            jobs = [dict(L=L, zone_mask=m, seed=515, nsamples=8)]
+            gn, gm, _, _ = run_batch(jobs, tune=autotune.lookup(L, m) or None)
+            assert_same(jobs, gn, gm, *oracle_batch(jobs))
