@@ -188,8 +188,29 @@ def main():
     sp = summarise(plain, args.steps, S, z)
     sl = summarise(learn, args.steps, S, z)
 
-    kernel_ms = sl["sweep_kernel_ms"]
-    achieved = sl["sweep_alg_bytes"] / (kernel_ms / 1e3) / 1e9
+    # the sweep kernel: algorithmic bytes of a step's launches over their time
+    # (HIP events on the launch stream), i.e. per launch over the average
+    # launch duration
+    sweep_ms_step = sl["phase_ms_per_step"]["sweep_ms"]
+    launches = max(1.0, learn["phase"]["sweep_launches"] / args.steps)
+    kernel_ms = sweep_ms_step / launches
+    achieved = sl["sweep_alg_bytes"] / (sweep_ms_step / 1e3) / 1e9
+    traffic = None
+    rec_path = os.path.join(ROOT, "profiles", "nz_sweep_L16_compact_x1000_learned.json")
+    if L == 16 and S == 1000 and os.path.exists(rec_path):
+        from paper_2607_18991_amd import profile_summary
+
+        rec = json.load(open(rec_path))
+        if rec.get("source_sha1") == profile_summary.source_sha1():
+            traffic = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+    # the keys kernel: integer VALU work of Philox4x32-10 (one block of 10
+    # rounds, each two 32x32->64 products and four XORs, serves two sites) plus
+    # four operations of classification per site, against 256 CUs x 64 lanes x
+    # 2.4 GHz of 32-bit integer operations
+    keys_ops_per_site = 10 * 6 / 2 + 4
+    keyed_sites = float(N) * len(learn["ns"])
+    keys_achieved = keyed_sites * keys_ops_per_site / (sl["phase_ms_per_step"]["keys_ms"] / 1e3) / 1e12
+    alu_peak = 256 * 64 * 2.4e9 / 1e12
     out = {
         "metric": "site additions/s and samples/s at L=16, zones 1-7; learned-prefill vs plain speedup",
         "value": sl["site_additions_per_s"],
@@ -212,8 +233,12 @@ def main():
         "learned": sl,
         "plain": sp,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None, "kernel": "nz_sweep_kernel",
-                     "kernel_ms": kernel_ms},
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "nz_sweep_kernel",
+                     "kernel_ms": kernel_ms, "launches_per_step": launches,
+                     "alg_bytes_per_launch": sl["sweep_alg_bytes"] / launches},
+        "roofline_keys": {"bound": "alu", "achieved": keys_achieved, "peak": alu_peak, "unit": "Tops/s",
+                          "frac": keys_achieved / alu_peak, "kernel": "nz_keys_kernel",
+                          "ops_per_site": keys_ops_per_site},
     }
     if args.l24_samples > 0:
         # the same comparison at L = 24 (7,962,624 sites): the 7 compact and 20

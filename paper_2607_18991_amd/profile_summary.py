@@ -1,0 +1,117 @@
+"""Summaries of rocprofv3 runs of the benchmark for the profiles/ folder.
+
+From a kernel-trace run (--kernel-trace --stats) and two counter runs
+(--pmc FETCH_SIZE, --pmc WRITE_SIZE) of the same command, it writes
+profiles/<name>.md (per-kernel time and HBM traffic, with the commands) and
+profiles/<name>.json, the traffic per launch of the sweep kernel together
+with the SHA-1 of the kernel source it was measured on; bench.py reports that
+traffic only while the source is unchanged.
+
+Counter scaling: FETCH_SIZE and WRITE_SIZE are KiB per dispatch; a plain
+device copy of 1 GiB reads FETCH_SIZE = 0.5 GiB and WRITE_SIZE = 1 GiB on
+this chip, so fetched bytes are FETCH_SIZE * 1024 * FETCH_SCALE and written
+bytes WRITE_SIZE * 1024 * WRITE_SCALE.
+"""
+from __future__ import annotations
+
+import argparse
+import csv
+import hashlib
+import json
+import os
+from collections import defaultdict
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+KERNEL_SOURCE = os.path.join(HERE, "csrc", "nz_kernels.hip")
+FETCH_SCALE = 2.0
+WRITE_SCALE = 1.0
+
+
+def source_sha1(path: str = KERNEL_SOURCE) -> str:
+    with open(path, "rb") as f:
+        return hashlib.sha1(f.read()).hexdigest()
+
+
+def short(name: str) -> str:
+    n = name[5:] if name.startswith("void ") else name
+    return n.split("(")[0]
+
+
+def _find(dirname: str, suffix: str) -> str:
+    for root, _, files in os.walk(dirname):
+        for f in files:
+            if f.endswith(suffix):
+                return os.path.join(root, f)
+    raise FileNotFoundError(f"no *{suffix} under {dirname}")
+
+
+def kernel_stats(dirname: str):
+    rows = []
+    for r in csv.DictReader(open(_find(dirname, "kernel_stats.csv"))):
+        rows.append(dict(kernel=short(r["Name"]), calls=int(r["Calls"]), total_ms=float(r["TotalDurationNs"]) / 1e6,
+                         avg_ms=float(r["AverageNs"]) / 1e6, pct=float(r["Percentage"])))
+    return rows
+
+
+def counters(dirname: str, counter: str):
+    """Per kernel: (dispatches, summed counter value in KiB)."""
+    agg = defaultdict(lambda: [0, 0.0])
+    for r in csv.DictReader(open(_find(dirname, "counter_collection.csv"))):
+        if r["Counter_Name"] != counter:
+            continue
+        k = short(r["Kernel_Name"])
+        agg[k][0] += 1
+        agg[k][1] += float(r["Counter_Value"])
+    return agg
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--stats", required=True, help="output folder of the --kernel-trace --stats run")
+    ap.add_argument("--fetch", required=True, help="output folder of the --pmc FETCH_SIZE run")
+    ap.add_argument("--write", required=True, help="output folder of the --pmc WRITE_SIZE run")
+    ap.add_argument("--name", required=True)
+    ap.add_argument("--title", required=True)
+    ap.add_argument("--commands", required=True, help="text file with the three commands")
+    ap.add_argument("--steps", type=int, default=2, help="bench steps in the stats run (warm-up included)")
+    ap.add_argument("--sweep", default="nz::nz_sweep_kernel")
+    ap.add_argument("--outdir", default=os.path.join(HERE, "..", "profiles"))
+    args = ap.parse_args()
+
+    stats = kernel_stats(args.stats)
+    fetch = counters(args.fetch, "FETCH_SIZE")
+    write = counters(args.write, "WRITE_SIZE")
+    lines = [f"# {args.title}", "", "Commands (GPU box, from the repository root):", "", "```"]
+    lines += open(args.commands).read().strip().splitlines()
+    lines += ["```", "", f"Kernel time ({args.steps} bench steps in the trace run):", "",
+              "| kernel | calls | total ms | average ms | % |", "|---|---|---|---|---|"]
+    for r in stats:
+        lines.append(f"| `{r['kernel']}` | {r['calls']} | {r['total_ms']:.3f} | {r['avg_ms']:.3f} | {r['pct']:.1f} |")
+    lines += ["", f"HBM traffic (one step; FETCH_SIZE x {FETCH_SCALE:g}, WRITE_SIZE x {WRITE_SCALE:g}, "
+                  "calibrated on a 1 GiB device copy):", "",
+              "| kernel | dispatches | fetched GB | written GB |", "|---|---|---|---|"]
+    for k in sorted(set(fetch) | set(write), key=lambda k: -(fetch.get(k, [0, 0])[1] + write.get(k, [0, 0])[1])):
+        f_gb = fetch.get(k, [0, 0.0])[1] * 1024 * FETCH_SCALE / 1e9
+        w_gb = write.get(k, [0, 0.0])[1] * 1024 * WRITE_SCALE / 1e9
+        n = max(fetch.get(k, [0, 0])[0], write.get(k, [0, 0])[0])
+        if f_gb + w_gb < 1e-3:
+            continue
+        lines.append(f"| `{k}` | {n} | {f_gb:.2f} | {w_gb:.2f} |")
+    sweep_f = sum(v[1] for k, v in fetch.items() if k.startswith(args.sweep)) * 1024 * FETCH_SCALE
+    sweep_w = sum(v[1] for k, v in write.items() if k.startswith(args.sweep)) * 1024 * WRITE_SCALE
+    launches = max(1, sum(v[0] for k, v in fetch.items() if k.startswith(args.sweep)))
+    rec = {"kernel": args.sweep, "launches": launches, "fetch_bytes_per_launch": sweep_f / launches,
+           "write_bytes_per_launch": sweep_w / launches, "source_sha1": source_sha1()}
+    lines += ["", f"Sweep kernel per launch: {rec['fetch_bytes_per_launch'] / 1e9:.3f} GB fetched, "
+                  f"{rec['write_bytes_per_launch'] / 1e9:.3f} GB written over {launches} launches; kernel source "
+                  f"SHA-1 {rec['source_sha1'][:12]}.", ""]
+    os.makedirs(args.outdir, exist_ok=True)
+    with open(os.path.join(args.outdir, args.name + ".md"), "w") as f:
+        f.write("\n".join(lines))
+    with open(os.path.join(args.outdir, args.name + ".json"), "w") as f:
+        json.dump(rec, f, indent=1)
+    print("\n".join(lines))
+
+
+if __name__ == "__main__":
+    main()
