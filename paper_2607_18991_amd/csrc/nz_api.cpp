@@ -198,9 +198,11 @@ uint64_t rank_to_key(int64_t n, int64_t N)
 struct Sizes {
     uint64_t T0;
     int32_t nb, cap, shift, full, prefix_cap;
-    int64_t n0b;      // prefill rank after a first backoff (0: none planned)
-    uint64_t T0b;     // its key threshold
-    int32_t nbb;      // buckets of the backed-off band
+    // prefill ranks of the backoffs resolved inside the chunk: n0 - b, then
+    // n0 - 3b (0: none planned), their key thresholds and band buckets
+    int64_t n0b[2];
+    uint64_t T0b[2];
+    int32_t nbb[2];
     size_t par, occ, keys, sites, counts, prefix, total;
 };
 
@@ -224,12 +226,16 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
         return static_cast<int32_t>(std::max<unsigned __int128>(1, (span + w - 1) / w));
     };
     s.nb = buckets(s.T0);
-    // a first backoff is resolved inside the chunk, so the band region is sized
-    // for the backed-off band as well
-    s.n0b = (p.n0 > 0 && p.backoff > 0 && p.n0 - p.backoff > 0) ? p.n0 - p.backoff : 0;
-    s.T0b = s.n0b > 0 ? rank_to_key(s.n0b, N) : 0;
-    s.nbb = s.n0b > 0 ? buckets(s.T0b) : 0;
-    const int32_t nb_alloc = std::max(s.nb, s.nbb);
+    // two backoffs are resolved inside the chunk, so the band region is sized
+    // for the backed-off bands as well
+    s.n0b[0] = (p.n0 > 0 && p.backoff > 0 && p.n0 - p.backoff > 0) ? p.n0 - p.backoff : 0;
+    s.n0b[1] = (s.n0b[0] > 0 && s.n0b[0] - 2 * p.backoff > 0) ? s.n0b[0] - 2 * p.backoff : 0;
+    int32_t nb_alloc = s.nb;
+    for (int l = 0; l < 2; ++l) {
+        s.T0b[l] = s.n0b[l] > 0 ? rank_to_key(s.n0b[l], N) : 0;
+        s.nbb[l] = s.n0b[l] > 0 ? buckets(s.T0b[l]) : 0;
+        nb_alloc = std::max(nb_alloc, s.nbb[l]);
+    }
     const double mean = std::ldexp(static_cast<double>(N), shift - 64);
     int cap = static_cast<int>(std::ceil(mean + 8.0 * std::sqrt(mean) + 16.0));
     cap = (cap + 15) / 16 * 16;
@@ -529,29 +535,31 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 const int32_t bx_site = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(1024, (max_site + 1023) / 1024)));
                 HIP_TRY(nz::launch_prefill(d_desc, d_list, static_cast<int32_t>(prefill_list.size()), bx_hook, bx_site, d_tabs, ws,
                                            d_state, st));
-                // Resolve first backoffs inside the chunk: samples whose bulk state
-                // already spans are re-keyed and re-labelled from n0 - backoff now,
-                // so they join this chunk's sweep instead of a later redo round.
-                std::vector<NzState> st0(n);
-                HIP_TRY(hipMemcpyAsync(st0.data(), d_state, n * sizeof(NzState), hipMemcpyDeviceToHost, st));
-                HIP_TRY(hipStreamSynchronize(st));
-                std::vector<int32_t> again;
-                for (int32_t di : prefill_list) {
-                    if (st0[di].status != NZ_ST_BACKOFF) continue;
-                    const int32_t ci = chunk_of_desc[di];
-                    const Sizes &s = sizes[ci];
-                    if (s.n0b <= 0) continue;   // no first backoff planned: the redo round takes it
-                    Plan &p = chunk[ci];
-                    ++g_stats[3];
-                    if (h_backoffs) ++h_backoffs[p.job];
-                    p.n0 = s.n0b;
-                    p.backoff *= 2;   // the next backoff, if any, doubles the step
-                    desc[di].T0 = s.T0b;
-                    desc[di].nb = s.nbb;
-                    max_nb = std::max(max_nb, s.nbb);
-                    again.push_back(di);
-                }
-                if (!again.empty()) {
+                // Resolve backoffs inside the chunk: samples whose bulk state already
+                // spans are re-keyed and re-labelled from n0 - b, and if that spans
+                // too from n0 - 3b, so they join this chunk's sweep instead of a
+                // later redo round.
+                for (int level = 0; level < 2; ++level) {
+                    std::vector<NzState> st0(n);
+                    HIP_TRY(hipMemcpyAsync(st0.data(), d_state, n * sizeof(NzState), hipMemcpyDeviceToHost, st));
+                    HIP_TRY(hipStreamSynchronize(st));
+                    std::vector<int32_t> again;
+                    for (int32_t di : prefill_list) {
+                        if (st0[di].status != NZ_ST_BACKOFF) continue;
+                        const int32_t ci = chunk_of_desc[di];
+                        const Sizes &s = sizes[ci];
+                        if (s.n0b[level] <= 0) continue;   // not planned: the redo round takes it
+                        Plan &p = chunk[ci];
+                        ++g_stats[3];
+                        if (h_backoffs) ++h_backoffs[p.job];
+                        p.n0 = s.n0b[level];
+                        p.backoff *= 2;   // the next backoff doubles the step
+                        desc[di].T0 = s.T0b[level];
+                        desc[di].nb = s.nbb[level];
+                        max_nb = std::max(max_nb, s.nbb[level]);
+                        again.push_back(di);
+                    }
+                    if (again.empty()) break;
                     std::stable_sort(again.begin(), again.end(), [&](int32_t a, int32_t b) { return desc[a].N < desc[b].N; });
                     const int32_t na = static_cast<int32_t>(again.size());
                     HIP_TRY(hipMemcpyAsync(d_desc, desc.data(), n * sizeof(NzSample), hipMemcpyHostToDevice, st));

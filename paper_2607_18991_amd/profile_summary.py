@@ -4,8 +4,8 @@ From a kernel-trace run (--kernel-trace --stats) and two counter runs
 (--pmc FETCH_SIZE, --pmc WRITE_SIZE) of the same command, it writes
 profiles/<name>.md (per-kernel time and HBM traffic, with the commands) and
 profiles/<name>.json, the traffic per launch of the sweep kernel together
-with the SHA-1 of the kernel source it was measured on; bench.py reports that
-traffic only while the source is unchanged.
+with the SHA-1 of the kernel and launch-planner sources it was measured on;
+bench.py reports that traffic only while those sources are unchanged.
 
 Counter scaling: FETCH_SIZE and WRITE_SIZE are KiB per dispatch; a plain
 device copy of 1 GiB reads FETCH_SIZE = 0.5 GiB and WRITE_SIZE = 1 GiB on
@@ -22,14 +22,18 @@ import os
 from collections import defaultdict
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-KERNEL_SOURCE = os.path.join(HERE, "csrc", "nz_kernels.hip")
+# the kernels and the host planner that decides their launches
+KERNEL_SOURCES = (os.path.join(HERE, "csrc", "nz_kernels.hip"), os.path.join(HERE, "csrc", "nz_api.cpp"))
 FETCH_SCALE = 2.0
 WRITE_SCALE = 1.0
 
 
-def source_sha1(path: str = KERNEL_SOURCE) -> str:
-    with open(path, "rb") as f:
-        return hashlib.sha1(f.read()).hexdigest()
+def source_sha1(paths=KERNEL_SOURCES) -> str:
+    h = hashlib.sha1()
+    for p in paths:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def short(name: str) -> str:
