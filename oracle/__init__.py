@@ -61,6 +61,8 @@ def lib():
         L.nzo_prefix_labels.restype = ctypes.c_int
         L.nzo_canonical.argtypes = [P, i64, P, i64, P]
         L.nzo_canonical.restype = ctypes.c_int
+        L.nzo_convolve_window.argtypes = [P, i64, i64, i64, P, i64, P, P]
+        L.nzo_convolve_window.restype = ctypes.c_int
         _lib = L
     return _lib
 
@@ -153,6 +155,28 @@ def prefix_labels(L: int, mask: int, order_arr, n: int) -> np.ndarray:
     lab = np.zeros(L**5, dtype=np.int32)
     _check(lib().nzo_prefix_labels(L, mask, _ptr(o), n, _ptr(lab)), "prefix_labels")
     return lab
+
+
+def convolve_window(Q, n_lo: int, N: int, p_grid):
+    """(out, cover): binomial convolution of Q[n - n_lo], n in [n_lo, n_lo + len(Q))."""
+    q = np.ascontiguousarray(Q, dtype=np.float64)
+    p = np.ascontiguousarray(p_grid, dtype=np.float64)
+    out = np.zeros(len(p), dtype=np.float64)
+    cov = np.zeros(len(p), dtype=np.float64)
+    _check(lib().nzo_convolve_window(_ptr(q), int(n_lo), int(n_lo + len(q)), int(N), _ptr(p), len(p), _ptr(out),
+                                     _ptr(cov)), "convolve_window")
+    return out, cov
+
+
+def smax_window(L: int, mask: int, seed: int, sample0: int, nsamples: int, n_lo: int, n_hi: int) -> np.ndarray:
+    """Sum over samples sample0 .. of S_max(n), n in [n_lo, n_hi) (the largest
+    cluster size after n occupied sites), from the serial sweep run past n*."""
+    acc = np.zeros(n_hi - n_lo, dtype=np.int64)
+    for s in range(sample0, sample0 + nsamples):
+        o = order(L, seed, s)
+        _, _, sm = sweep_order(L, mask, o[:n_hi], smax=True, run_to_end=True)
+        acc += sm[n_lo - 1:n_hi - 1]
+    return acc
 
 
 def canonical(hist, p_grid) -> np.ndarray:

@@ -445,3 +445,46 @@ int nzo_canonical(const uint64_t *hist, int64_t hist_len, const double *p, int64
     free(w);
     return rc;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Binomial convolution of an observable known on a window of n: eq. (5)-(6)
+ * need P_max(p) = sum_n C(N,n) p^n (1-p)^(N-n) S_max(n) / N; only n in
+ * [n_lo, n_hi) are summed.  out[j] = sum_{window} B(n) Q[n - n_lo] and
+ * cover[j] = sum_{window} B(n), with B the binomial pmf of (N, p[j]) (weights
+ * built outward from the mode by the ratio recurrence, normalised by their sum
+ * over 0..N). */
+int nzo_convolve_window(const double *Q, int64_t n_lo, int64_t n_hi, int64_t N, const double *p, int64_t np,
+                        double *out, double *cover)
+{
+    if (N < 1 || n_lo < 0 || n_hi > N + 1 || n_lo >= n_hi || !Q || np < 0 || (np > 0 && (!p || !out))) return -1;
+    long double *w = (long double *)malloc((size_t)(N + 1) * sizeof(long double));
+    if (!w) return -1;
+    int rc = 0;
+    for (int64_t j = 0; j < np; ++j) {
+        long double q = p[j];
+        if (!(q >= 0.0L && q <= 1.0L)) { rc = -1; break; }
+        for (int64_t n = 0; n <= N; ++n) w[n] = 0.0L;
+        if (q == 0.0L) w[0] = 1.0L;
+        else if (q == 1.0L) w[N] = 1.0L;
+        else {
+            int64_t m = (int64_t)((long double)(N + 1) * q);
+            if (m > N) m = N;
+            long double ratio_up = q / (1.0L - q);
+            w[m] = 1.0L;
+            for (int64_t n = m; n < N; ++n)
+                w[n + 1] = w[n] * ((long double)(N - n) / (long double)(n + 1)) * ratio_up;
+            for (int64_t n = m; n > 0; --n)
+                w[n - 1] = w[n] * ((long double)n / (long double)(N - n + 1)) / ratio_up;
+        }
+        long double sw = 0.0L, swq = 0.0L, swin = 0.0L;
+        for (int64_t n = 0; n <= N; ++n) sw += w[n];
+        for (int64_t n = n_lo; n < n_hi; ++n) {
+            swq += w[n] * (long double)Q[n - n_lo];
+            swin += w[n];
+        }
+        out[j] = (double)(swq / sw);
+        if (cover) cover[j] = (double)(swin / sw);
+    }
+    free(w);
+    return rc;
+}

@@ -88,6 +88,13 @@ int nzo_prefix_labels(int32_t L, uint32_t mask, const uint32_t *order, int64_t n
 int nzo_canonical(const uint64_t *hist, int64_t hist_len, const double *p, int64_t np,
                   double *R);
 
+/* Binomial convolution of an observable Q known for n in [n_lo, n_hi):
+ * out[j] = sum_{n_lo <= n < n_hi} B(n; N, p[j]) Q[n - n_lo] and, if cover is
+ * non-NULL, cover[j] = sum of the same weights (1 when the window holds the
+ * whole binomial mass).  Long double.  Returns 0 or -1. */
+int nzo_convolve_window(const double *Q, int64_t n_lo, int64_t n_hi, int64_t N, const double *p, int64_t np,
+                        double *out, double *cover);
+
 #ifdef __cplusplus
 }
 #endif
