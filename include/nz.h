@@ -84,6 +84,36 @@ int nz_canonical(const uint64_t *hist, int64_t hist_len, const double *p_grid, i
                  double *R);
 
 /*
+ * nz_smax_window -- the largest cluster S_max(n) after n occupied sites, summed
+ * over samples sample0 .. sample0+nsamples-1, for n in [n_lo, n_hi): the
+ * observable of eqs. (5)-(6) (P_max = S_max / L^5 before the convolution).
+ * The sweep runs on past n* through the window, one site per step.
+ *   n0         -1: plain sweep; else 0 <= n0 < n_lo: the sites of rank < n0
+ *              (keys below floor(n0 / N * 2^64)) are labelled in bulk first
+ *              (if that count reaches the window, n0 is halved and the sample
+ *              redone);
+ *   1 <= n_lo < n_hi <= N;
+ *   smax_sum   HOST array of n_hi - n_lo uint64, written (sum over samples of
+ *              S_max(n_lo + k) in entry k).
+ * Synchronous; allocates and frees its own device memory; current device,
+ * default stream.
+ */
+int nz_smax_window(int32_t L, uint32_t zone_mask, int32_t boundary, uint64_t seed, int64_t sample0,
+                   int64_t nsamples, int64_t n0, int64_t n_lo, int64_t n_hi, uint64_t *smax_sum);
+
+/*
+ * nz_convolve_window -- binomial convolution of an observable known on a
+ * window of n (eqs. (5)-(6): P_max(p) from <S_max(n)> / N):
+ *   out[j]   = sum_{n_lo <= n < n_hi} C(N,n) p_j^n (1-p_j)^(N-n) Q[n - n_lo],
+ *   cover[j] = sum of the same weights (1 when the window holds the whole
+ *              binomial mass at p_j); cover may be NULL.
+ *   0 <= n_lo < n_hi <= N + 1; HOST arrays; FP64, weights built outward from
+ * the mode like nz_canonical.
+ */
+int nz_convolve_window(const double *Q, int64_t n_lo, int64_t n_hi, int64_t N, const double *p_grid,
+                       int64_t np, double *out, double *cover);
+
+/*
  * Batched device API.  One nz_job describes nsamples consecutive samples
  * (Philox sample indices sample0 ..) of one (L, zone_mask) lattice.
  *   n0        -1: plain sweep from the empty lattice.

@@ -186,6 +186,7 @@ struct Plan {
     int32_t shift_adj;   // extra halvings of the bucket width
     int32_t prefix_mul;  // prefill list capacity multiplier
     double prio;
+    int64_t win_lo, win_hi;   // smax mode: S_max(n) for n in [win_lo, win_hi) (win_hi = 0: off)
 };
 
 uint64_t rank_to_key(int64_t n, int64_t N)
@@ -203,7 +204,7 @@ struct Sizes {
     int64_t n0b[2];
     uint64_t T0b[2];
     int32_t nbb[2];
-    size_t par, occ, keys, sites, counts, prefix, total;
+    size_t par, occ, keys, sites, counts, prefix, win, total;
 };
 
 Sizes plan_sizes(const Plan &p, int bucket_log2)
@@ -256,7 +257,8 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
     s.sites = align_up(static_cast<size_t>(nb_alloc) * s.cap * 4);
     s.counts = align_up(static_cast<size_t>(nb_alloc) * 4);
     s.prefix = align_up(static_cast<size_t>(s.prefix_cap) * 4);
-    s.total = s.par + s.occ + s.keys + s.sites + s.counts + s.prefix;
+    s.win = p.win_hi > 0 ? align_up(static_cast<size_t>(p.win_hi - p.win_lo) * 4) : 0;
+    s.total = s.par + s.occ + s.keys + s.sites + s.counts + s.prefix + s.win;
     return s;
 }
 
@@ -370,8 +372,15 @@ struct TablePool {
     }
 };
 
+// smax mode of a whole batch: every sample records S_max(n) for n in
+// [win_lo, win_hi) and the chunks add the windows of their samples into out.
+struct SmaxReq {
+    int64_t win_lo, win_hi;
+    uint64_t *d_out;
+};
+
 int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_t *d_nstar, int32_t *d_mass,
-              int32_t *h_backoffs, const Tune &tune, hipStream_t st)
+              int32_t *h_backoffs, const Tune &tune, hipStream_t st, const SmaxReq *smax = nullptr)
 {
     Device dev;
     if (int rc = device_info(dev)) return rc;
@@ -403,6 +412,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             p.shift_adj = 0;
             p.prefix_mul = 1;
             p.prio = J.prio > 0 ? J.prio : static_cast<double>(std::max<int64_t>(1, p.band_hi - p.n0)) * (1.0 + z / 64.0);
+            p.win_lo = smax ? smax->win_lo : 0;
+            p.win_hi = smax ? smax->win_hi : 0;
             todo.push_back(p);
         }
     }
@@ -475,6 +486,10 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 d.off_sites = off; off += s.sites;
                 d.off_counts = off; off += s.counts;
                 d.off_prefix = off; off += s.prefix;
+                d.off_win = off; off += s.win;
+                d.smax_mode = p.win_hi > 0 ? 1 : 0;
+                d.win_lo = static_cast<int32_t>(p.win_lo);
+                d.win_hi = static_cast<int32_t>(p.win_hi);
                 out_index[di] = p.out;
                 chunk_of_desc[di] = ci;
                 desc_of_chunk[ci] = di;
@@ -534,7 +549,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 const int32_t bx_hook = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(256, (max_site + 1023) / 1024)));
                 const int32_t bx_site = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(1024, (max_site + 1023) / 1024)));
                 HIP_TRY(nz::launch_prefill(d_desc, d_list, static_cast<int32_t>(prefill_list.size()), bx_hook, bx_site, d_tabs, ws,
-                                           d_state, st));
+                                           d_state, smax != nullptr, st));
                 // Resolve backoffs inside the chunk: samples whose bulk state already
                 // spans are re-keyed and re-labelled from n0 - b, and if that spans
                 // too from n0 - 3b, so they join this chunk's sweep instead of a
@@ -571,7 +586,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                         HIP_TRY(nz::launch_keys(d_desc, d_list, a, b - a, desc[again[a]].N, ws, d_state, st));
                         a = b;
                     }
-                    HIP_TRY(nz::launch_prefill(d_desc, d_list, na, bx_hook, bx_site, d_tabs, ws, d_state, st));
+                    HIP_TRY(nz::launch_prefill(d_desc, d_list, na, bx_hook, bx_site, d_tabs, ws, d_state, smax != nullptr, st));
                 }
             }
             if (pe) HIP_TRY(hipEventRecord(pe->ev[2], st));
@@ -611,6 +626,9 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             args.blk_old = env_blk_old();
             args.blk_zmax = blk_zmax;
             HIP_TRY(nz::launch_sweep(nch_for(max_z), residency, block, args, d_nstar, d_mass, d_outidx, grid, wg_waves, st));
+            if (smax)
+                HIP_TRY(nz::launch_winsum(d_desc, d_state, n, static_cast<int32_t>(smax->win_hi - smax->win_lo), ws,
+                                          smax->d_out, st));
             if (pe) HIP_TRY(hipEventRecord(pe->ev[4], st));
 
             // ---- read back and schedule the redo of unfinished samples
@@ -864,6 +882,115 @@ NZ_API int nz_sweep(int32_t L, uint32_t zone_mask, int32_t boundary, int64_t nsa
     (void)hipFree(dn);
     (void)hipFree(dm);
     return rc;
+}
+
+NZ_API int nz_smax_window(int32_t L, uint32_t zone_mask, int32_t boundary, uint64_t seed, int64_t sample0,
+                          int64_t nsamples, int64_t n0, int64_t n_lo, int64_t n_hi, uint64_t *smax_sum)
+{
+    nz_job j{};
+    j.L = L;
+    j.zone_mask = zone_mask;
+    j.boundary = boundary;
+    j.seed = seed;
+    j.sample0 = sample0;
+    j.nsamples = nsamples;
+    j.n0 = n0 > 0 ? n0 : -1;
+    j.backoff = 0;   // a prefill that reaches the window halves n0
+    if (int rc = check_job(j, 0)) return rc;
+    const int64_t N = pow5(L);
+    if (n_lo < 1 || n_hi <= n_lo || n_hi > N)
+        return fail(NZ_EINVAL, "window [%lld, %lld) outside [1, N = %lld]", (long long)n_lo, (long long)n_hi,
+                    (long long)N);
+    if (n0 >= n_lo) return fail(NZ_EINVAL, "n0 = %lld must lie below the window start %lld", (long long)n0, (long long)n_lo);
+    if (!smax_sum) return fail(NZ_EINVAL, "smax_sum is NULL");
+    if (nsamples > 0x7FFFFFFF) return fail(NZ_EINVAL, "nsamples too large");
+    const int64_t W = n_hi - n_lo;
+    for (int64_t k = 0; k < W; ++k) smax_sum[k] = 0;
+    if (nsamples == 0) return NZ_OK;
+    // the key band ends a little beyond the window, so a band that runs short is rare
+    j.band_hi = std::min<int64_t>(N, n_hi + 4 * static_cast<int64_t>(std::sqrt(static_cast<double>(n_hi))) + 1024);
+    Tune t;
+    t.dcap = env_dcap();
+    size_t bytes = 0;
+    try {
+        bytes = batch_bytes(&j, 1, t) + static_cast<size_t>(std::min<int64_t>(nsamples, kMaxChunk) + 1) *
+                                            align_up(static_cast<size_t>(W) * 4);
+    } catch (...) {
+        return fail(NZ_ENOMEM, "host allocation failed");
+    }
+    size_t freeb = 0, totalb = 0;
+    HIP_TRY(hipMemGetInfo(&freeb, &totalb));
+    bytes = std::min(bytes, freeb / 2);
+    void *ws = nullptr;
+    int32_t *dn = nullptr;
+    uint64_t *dsum = nullptr;
+    if (hipMalloc(&ws, bytes) != hipSuccess) return fail(NZ_ENOMEM, "hipMalloc of %zu workspace bytes failed", bytes);
+    if (hipMalloc(reinterpret_cast<void **>(&dn), nsamples * 4) != hipSuccess ||
+        hipMalloc(reinterpret_cast<void **>(&dsum), W * 8) != hipSuccess) {
+        (void)hipFree(ws);
+        (void)hipFree(dn);
+        return fail(NZ_ENOMEM, "hipMalloc of outputs failed");
+    }
+    int rc = NZ_OK;
+    if (hipMemset(dsum, 0, W * 8) != hipSuccess) rc = fail(NZ_EDEVICE, "clearing the window sums failed");
+    SmaxReq req{n_lo, n_hi, dsum};
+    if (rc == NZ_OK) {
+        try {
+            rc = run_batch(&j, 1, static_cast<uint8_t *>(ws), bytes, dn, nullptr, nullptr, t, nullptr, &req);
+        } catch (...) {
+            rc = fail(NZ_ENOMEM, "host allocation failed");
+        }
+    }
+    if (rc == NZ_OK && hipMemcpy(smax_sum, dsum, W * 8, hipMemcpyDeviceToHost) != hipSuccess)
+        rc = fail(NZ_EDEVICE, "copy of the window sums failed");
+    (void)hipFree(ws);
+    (void)hipFree(dn);
+    (void)hipFree(dsum);
+    return rc;
+}
+
+// Binomial convolution of an observable on a window (eqs. (5)-(6) need
+// P_max(p) = <S_max(n)>/N convolved with the binomial of (N, p)): the same
+// weights as nz_canonical, summed over n in [n_lo, n_hi) only.
+NZ_API int nz_convolve_window(const double *Q, int64_t n_lo, int64_t n_hi, int64_t N, const double *p_grid, int64_t np,
+                              double *out, double *cover)
+{
+    if (N < 1 || n_lo < 0 || n_hi > N + 1 || n_lo >= n_hi || !Q)
+        return fail(NZ_EINVAL, "window [%lld, %lld) outside [0, N + 1 = %lld]", (long long)n_lo, (long long)n_hi,
+                    (long long)(N + 1));
+    if (np < 0 || (np > 0 && (!p_grid || !out))) return fail(NZ_EINVAL, "bad p grid or output");
+    for (int64_t k = 0; k < np; ++k)
+        if (!(p_grid[k] >= 0.0 && p_grid[k] <= 1.0)) return fail(NZ_EINVAL, "p_grid[%lld] outside [0, 1]", (long long)k);
+    for (int64_t k = 0; k < np; ++k) {
+        const double p = p_grid[k];
+        int64_t mode = p == 0.0 ? 0 : (p == 1.0 ? N : static_cast<int64_t>(std::floor((N + 1) * p)));
+        if (mode > N) mode = N;
+        auto q = [&](int64_t n) { return n >= n_lo && n < n_hi ? Q[n - n_lo] : 0.0; };
+        auto in = [&](int64_t n) { return n >= n_lo && n < n_hi ? 1.0 : 0.0; };
+        double sw = 1.0, swq = q(mode), swin = in(mode);
+        if (p > 0.0 && p < 1.0) {
+            const double up = p / (1.0 - p);
+            double w = 1.0;
+            for (int64_t n = mode; n < N; ++n) {
+                w *= static_cast<double>(N - n) / static_cast<double>(n + 1) * up;
+                if (w < 1e-300) break;
+                sw += w;
+                swq += w * q(n + 1);
+                swin += w * in(n + 1);
+            }
+            w = 1.0;
+            for (int64_t n = mode; n > 0; --n) {
+                w *= static_cast<double>(n) / static_cast<double>(N - n + 1) / up;
+                if (w < 1e-300) break;
+                sw += w;
+                swq += w * q(n - 1);
+                swin += w * in(n - 1);
+            }
+        }
+        out[k] = swq / sw;
+        if (cover) cover[k] = swin / sw;
+    }
+    return NZ_OK;
 }
 
 // Binomial convolution (Sec. II.B): weights C(N,n) p^n (1-p)^(N-n) are formed

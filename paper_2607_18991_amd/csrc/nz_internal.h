@@ -54,8 +54,11 @@ struct NzSample {
     int32_t tab;          // first entry of this sample's offset table
     int32_t z;            // number of offsets
     int32_t prefix_cap;   // capacity of the prefill site list
-    int32_t pad;
+    int32_t smax_mode;    // 1: track the largest cluster over [win_lo, win_hi) instead of stopping at n*
     uint64_t magic;       // ceil(2^64 / L) for exact division of site indices by L
+    uint64_t off_win;     // smax mode: S_max(n) for n in [win_lo, win_hi), uint32 each
+    int32_t win_lo;
+    int32_t win_hi;
 };
 
 // Per-sample result/state record written by the kernels.
@@ -64,6 +67,7 @@ struct NzState {
     int32_t nstar;
     int32_t mass;
     int32_t n0;           // sites occupied by the prefill (count of keys < T0)
+    int32_t smax;         // smax mode: largest cluster of the prefilled state
 };
 
 // Launch parameters of the sweep (one persistent launch per chunk).

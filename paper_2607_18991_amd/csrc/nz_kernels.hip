@@ -123,6 +123,7 @@ __global__ __launch_bounds__(256) void nz_clear_kernel(const NzSample *__restric
         s.nstar = 0;
         s.mass = 0;
         s.n0 = 0;
+        s.smax = 0;
         state[sid] = s;
     }
 }
@@ -550,9 +551,48 @@ __global__ __launch_bounds__(256) void nz_accum_kernel(const NzSample *__restric
             const uint32_t fl = border_flags(static_cast<uint32_t>(s), L, d.magic);
             if (fl) {
                 const uint32_t old = atomicOr(root, fl);
-                if (((old | fl) & NZ_FLAGS) == NZ_FLAGS) state[sid].status = NZ_ST_BACKOFF;
+                if (((old | fl) & NZ_FLAGS) == NZ_FLAGS && !d.smax_mode) state[sid].status = NZ_ST_BACKOFF;
             }
         }
+    }
+}
+
+// Largest cluster of the prefilled state (smax mode): every root word offers
+// its size.
+__global__ __launch_bounds__(256) void nz_rootmax_kernel(const NzSample *__restrict__ desc,
+                                                         const int32_t *__restrict__ list, int32_t nlist, int32_t bx,
+                                                         uint8_t *__restrict__ ws, NzState *__restrict__ state)
+{
+    int32_t y, x;
+    if (!xcd_slot(nlist, bx, y, x)) return;
+    const int sid = list[y];
+    const NzSample &d = desc[sid];
+    if (!d.smax_mode) return;
+    const int32_t n0 = state[sid].n0;
+    if (n0 > d.prefix_cap) return;
+    const int32_t *par = reinterpret_cast<const int32_t *>(ws + d.off_par);
+    const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
+    int32_t best = 0;
+    for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
+        const int32_t v = par[prefix[k]];
+        if (v < 0) best = max(best, static_cast<int32_t>(static_cast<uint32_t>(v) & NZ_SIZE));
+    }
+    if (best > 0) atomicMax(&state[sid].smax, best);
+}
+
+// Sum over the finished samples of a chunk of their S_max(n) windows (all
+// samples of an smax-mode batch share one window of w entries).
+__global__ __launch_bounds__(256) void nz_winsum_kernel(const NzSample *__restrict__ desc,
+                                                        const NzState *__restrict__ state, int32_t nsamp, int32_t w,
+                                                        const uint8_t *__restrict__ ws, uint64_t *__restrict__ out)
+{
+    for (int32_t i = blockIdx.x * 256 + static_cast<int32_t>(threadIdx.x); i < w; i += gridDim.x * 256) {
+        uint64_t sum = 0;
+        for (int32_t k = 0; k < nsamp; ++k) {
+            if (state[k].status != NZ_ST_DONE) continue;
+            sum += reinterpret_cast<const uint32_t *>(ws + desc[k].off_win)[i];
+        }
+        out[i] += sum;
     }
 }
 
@@ -1127,11 +1167,40 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         int32_t r = a.state[sid].n0;   // sites already occupied
         int32_t status = NZ_ST_BAND;
         int32_t nstar = 0, mass = 0;
+        // smax mode: the sweep runs on past n* and records the largest cluster
+        // after every addition with win_lo <= r < win_hi
+        const bool smax_mode = d.smax_mode != 0;
+        int32_t smax = a.state[sid].smax;
+        uint32_t *win = reinterpret_cast<uint32_t *>(a.ws + d.off_win);
+        // One addition done (r sites occupied, the new site's cluster has
+        // `total` sites and border flags `flags`): true when the sample is over.
+        auto finished = [&](uint32_t total, uint32_t flags) -> bool {
+            if (flags == NZ_FLAGS && nstar == 0) {
+                nstar = r;
+                mass = static_cast<int32_t>(total);
+                if (!smax_mode) {
+                    status = NZ_ST_DONE;
+                    return true;
+                }
+            }
+            if (smax_mode) {
+                smax = max(smax, static_cast<int32_t>(total));
+                if (r >= d.win_lo) win[r - d.win_lo] = static_cast<uint32_t>(smax);   // every lane, same value
+                if (r + 1 >= d.win_hi) {
+                    status = NZ_ST_DONE;
+                    return true;
+                }
+            }
+            return false;
+        };
 
-        // 64 sites per step up to the launch's z limit, one site per step above it
+        // 64 sites per step up to the launch's z limit, one site per step above
+        // it (and always one at a time in smax mode)
         bool use_block = false;
-        if constexpr (BLOCK) use_block = z <= a.blk_zmax;
-        if (use_block) {
+        if constexpr (BLOCK) use_block = z <= a.blk_zmax && !smax_mode;
+        if (smax_mode && r >= d.win_lo) {
+            status = NZ_ST_BACKOFF;   // the prefill covers part of the window: start lower
+        } else if (use_block) {
             // 64 sites of the band at a time; blocks do not cross buckets
             const uint32_t *counts = reinterpret_cast<const uint32_t *>(a.ws + d.off_counts);
             const uint32_t *sites = reinterpret_cast<const uint32_t *>(a.ws + d.off_sites);
@@ -1198,12 +1267,7 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
                 if (gotn == 1) nxt.prepare(m, lds, pcn, L, ostride, ocode);
                 uint32_t total, flags;
                 sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
-                if (flags == NZ_FLAGS) {
-                    status = NZ_ST_DONE;
-                    nstar = r;
-                    mass = static_cast<int32_t>(total);
-                    break;
-                }
+                if (finished(total, flags)) break;
                 if (gotn != 1) {
                     if (gotn < 0) status = NZ_ST_BUCKET;
                     break;
@@ -1217,12 +1281,7 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
                 cur.prepare(m, lds, pc, L, ostride, ocode);
                 uint32_t total, flags;
                 sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
-                if (flags == NZ_FLAGS) {
-                    status = NZ_ST_DONE;
-                    nstar = r;
-                    mass = static_cast<int32_t>(total);
-                    break;
-                }
+                if (finished(total, flags)) break;
                 got = bc.next(pc, lane);
                 if (got < 0) status = NZ_ST_BUCKET;
             }
@@ -1290,7 +1349,7 @@ hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int3
 }
 
 hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nlist, int32_t bx_hook, int32_t bx_site,
-                          const NzOffset *tabs, uint8_t *ws, NzState *state, hipStream_t st)
+                          const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, hipStream_t st)
 {
     if (nlist <= 0) return hipSuccess;
     const uint32_t slots8 = static_cast<uint32_t>((nlist + 7) / 8) * 8u;
@@ -1300,6 +1359,19 @@ hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nli
                        nlist, bx_site, ws, state);
     hipLaunchKernelGGL(nz_accum_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list, nlist,
                        bx_site, ws, state);
+    if (smax)
+        hipLaunchKernelGGL(nz_rootmax_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
+                           nlist, bx_site, ws, state);
+    return hipGetLastError();
+}
+
+hipError_t launch_winsum(const NzSample *desc, const NzState *state, int32_t nsamp, int32_t w, const uint8_t *ws,
+                         uint64_t *out, hipStream_t st)
+{
+    if (nsamp <= 0 || w <= 0) return hipSuccess;
+    const int32_t blocks = (w + 255) / 256;
+    const uint32_t grid = static_cast<uint32_t>(blocks < 4096 ? blocks : 4096);
+    hipLaunchKernelGGL(nz_winsum_kernel, dim3(grid), dim3(256), 0, st, desc, state, nsamp, w, ws, out);
     return hipGetLastError();
 }
 

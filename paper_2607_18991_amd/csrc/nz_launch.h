@@ -21,8 +21,13 @@ hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int3
                        hipStream_t st);
 
 // Bulk connected components for the samples listed in list[0..nlist).
+// smax: also the largest cluster of each smax-mode sample's prefilled state.
 hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nlist, int32_t bx_hook, int32_t bx_site,
-                          const NzOffset *tabs, uint8_t *ws, NzState *state, hipStream_t st);
+                          const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, hipStream_t st);
+
+// out[0..w) += sum over the chunk's finished samples 0..nsamp-1 of their S_max windows.
+hipError_t launch_winsum(const NzSample *desc, const NzState *state, int32_t nsamp, int32_t w, const uint8_t *ws,
+                         uint64_t *out, hipStream_t st);
 
 // residency: 0 HBM, 1 bitset in LDS, 2 bitset and parents in LDS.
 // nch in {1, 2, 4, 8, 14}.  block: 64 sites per wave step (the wave's LDS

@@ -29,7 +29,7 @@ EXPORTS = (
     "nz_last_error", "nz_abi_version", "nz_coordination", "nz_sweep", "nz_canonical",
     "nz_batch_workspace_bytes", "nz_sweep_batch", "nz_last_batch_stats",
     "nz_mlp_forward", "nz_mlp_backward", "nz_mlp_adam", "nz_set_timing", "nz_last_batch_timing",
-    "nz_mlp_loss",
+    "nz_mlp_loss", "nz_smax_window", "nz_convolve_window",
 )
 
 
@@ -79,6 +79,10 @@ def lib():
     L.nz_sweep.restype = ctypes.c_int
     L.nz_canonical.argtypes = [P, i64, P, i64, P]
     L.nz_canonical.restype = ctypes.c_int
+    L.nz_smax_window.argtypes = [i32, u32, i32, u64, i64, i64, i64, i64, i64, P]
+    L.nz_smax_window.restype = ctypes.c_int
+    L.nz_convolve_window.argtypes = [P, i64, i64, i64, P, i64, P, P]
+    L.nz_convolve_window.restype = ctypes.c_int
     L.nz_batch_workspace_bytes.argtypes = [P, i32, P, ctypes.POINTER(ctypes.c_size_t)]
     L.nz_batch_workspace_bytes.restype = ctypes.c_int
     L.nz_sweep_batch.argtypes = [P, i32, P, ctypes.c_size_t, P, P, P, P, P]
@@ -135,6 +139,25 @@ def nz_canonical(hist, p_grid) -> np.ndarray:
     R = np.zeros(len(p), dtype=np.float64)
     _check(lib().nz_canonical(_np_ptr(h), len(h), _np_ptr(p), len(p), _np_ptr(R)))
     return R
+
+
+def nz_smax_window(L: int, zone_mask: int, seed: int, sample0: int, nsamples: int, n_lo: int, n_hi: int,
+                   n0: int = -1, boundary: int = NZ_FREE) -> np.ndarray:
+    """Sum over the samples of S_max(n) for n in [n_lo, n_hi) (uint64 array)."""
+    out = np.zeros(max(n_hi - n_lo, 1), dtype=np.uint64)
+    _check(lib().nz_smax_window(L, zone_mask, boundary, seed, sample0, nsamples, n0, n_lo, n_hi, _np_ptr(out)))
+    return out[: n_hi - n_lo]
+
+
+def nz_convolve_window(Q, n_lo: int, N: int, p_grid):
+    """(out, cover): binomial convolution of Q[n - n_lo] over n in [n_lo, n_lo + len(Q))."""
+    q = np.ascontiguousarray(Q, dtype=np.float64)
+    p = np.ascontiguousarray(p_grid, dtype=np.float64)
+    out = np.zeros(max(len(p), 1), dtype=np.float64)
+    cov = np.zeros(max(len(p), 1), dtype=np.float64)
+    _check(lib().nz_convolve_window(_np_ptr(q), n_lo, n_lo + len(q), N, _np_ptr(p), len(p), _np_ptr(out),
+                                    _np_ptr(cov)))
+    return out[: len(p)], cov[: len(p)]
 
 
 def nz_sweep(L: int, zone_mask: int, nsamples: int, seed: int, boundary: int = NZ_FREE):

@@ -84,3 +84,27 @@ def test_canonical_rejects_bad_grid():
         nz.nz_canonical(np.ones(5, dtype=np.uint64), [0.5, 1.5])
     with pytest.raises(nz.NzError):
         nz.nz_canonical(np.zeros(5, dtype=np.uint64), [0.5])
+
+
+def test_convolve_window_matches_oracle():
+    import oracle
+
+    rng = np.random.default_rng(3)
+    for N, lo, hi in ((1, 0, 2), (50, 0, 51), (1000, 100, 300), (32768, 4000, 5500)):
+        Q = rng.random(hi - lo) * N
+        p = np.array([0.0, 0.003, 0.1408, 0.33, 1.0])
+        a, ca = nz.nz_convolve_window(Q, lo, N, p)
+        b, cb = oracle.convolve_window(Q, lo, N, p)
+        assert np.allclose(a, b, rtol=1e-12, atol=1e-12 * N) and np.allclose(ca, cb, atol=1e-12)
+
+
+def test_smax_window_validation():
+    for args in ((4, 1, 1, 0, 1, 0, 10), (4, 1, 1, 0, 1, 20, 10), (4, 1, 1, 0, 1, 5, 1025), (4, 1, 1, 0, 1, 5, 6)):
+        L, m, seed, s0, ns, lo, hi = args
+        n0 = 5 if args[-1] == 6 else -1
+        with pytest.raises(nz.NzError) as e:
+            nz.nz_smax_window(L, m, seed, s0, ns, lo, hi, n0=n0)
+        assert e.value.code == nz.NZ_EINVAL
+    with pytest.raises(nz.NzError) as e:
+        nz.nz_convolve_window(np.ones(3), 5, 4, [0.5])
+    assert e.value.code == nz.NZ_EINVAL

@@ -1,0 +1,53 @@
+"""S_max(n) windows (the observable of eqs. (5)-(6)) on the GPU against the
+oracle's serial sweep run past n*, sample sums compared exactly (GPU)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("L,mask,seed,s0,ns,lo,hi,n0", [
+    (3, 0x01, 4, 0, 40, 1, 243, -1),          # the whole lattice, n_hi = N
+    (4, 0x01, 7, 3, 50, 100, 400, -1),
+    (5, 0x03, 8, 0, 30, 50, 400, -1),
+    (6, 0x7F, 9, 0, 20, 5, 200, -1),
+    (6, 0x01, 10, 0, 16, 800, 1600, 500),     # prefilled below the window
+    (8, 0x01, 11, 0, 8, 3500, 5500, 3000),
+    (7, 0x0C, 12, 5, 12, 100, 900, 60),
+])
+def test_smax_window_matches_oracle(L, mask, seed, s0, ns, lo, hi, n0):
+    import oracle
+    from paper_2607_18991_amd import nz
+
+    got = nz.nz_smax_window(L, mask, seed, s0, ns, lo, hi, n0=n0)
+    want = oracle.smax_window(L, mask, seed, s0, ns, lo, hi)
+    assert got.dtype == np.uint64 and (got.astype(np.int64) == want).all()
+    assert (np.diff(want) >= 0).all()
+
+
+def test_prefill_reaching_the_window_is_redone():
+    """n0 just below the window: the count of keys below its threshold exceeds
+    n_lo for about half the samples, which are redone with a halved n0."""
+    import oracle
+    from paper_2607_18991_amd import nz
+
+    got = nz.nz_smax_window(6, 0x01, 13, 0, 24, 1000, 1300, n0=999)
+    want = oracle.smax_window(6, 0x01, 13, 0, 24, 1000, 1300)
+    assert (got.astype(np.int64) == want).all()
+
+
+def test_pmax_convolution_on_gpu_sums():
+    """P_max(p) of the GPU sums equals the oracle's convolution of the oracle's
+    sums, and the window holds the binomial mass in the middle of the grid."""
+    import oracle
+    from paper_2607_18991_amd import nz
+
+    L, mask, ns, lo, hi = 5, 0x01, 64, 300, 700
+    N = L**5
+    got = nz.nz_smax_window(L, mask, 21, 0, ns, lo, hi).astype(np.float64) / (ns * N)
+    want = oracle.smax_window(L, mask, 21, 0, ns, lo, hi).astype(np.float64) / (ns * N)
+    p = np.linspace(0.12, 0.18, 7)
+    a, ca = nz.nz_convolve_window(got, lo, N, p)
+    b, cb = oracle.convolve_window(want, lo, N, p)
+    assert np.allclose(a, b, rtol=1e-12) and np.allclose(ca, cb, atol=1e-12)
+    assert (ca[2:5] > 0.999).all()
