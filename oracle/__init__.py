@@ -62,6 +62,9 @@ def lib():
         L.nzo_canonical.argtypes = [P, i64, P, i64, P]
         L.nzo_canonical.restype = ctypes.c_int
         L.nzo_convolve_window.argtypes = [P, i64, i64, i64, P, i64, P, P]
+        L.nzo_sweep_order_bc.argtypes = [ctypes.c_int32, ctypes.c_uint32, ctypes.c_int, P, i64, P, P, P,
+                                         ctypes.c_int, ctypes.c_int]
+        L.nzo_sweep_order_bc.restype = ctypes.c_int
         L.nzo_convolve_window.restype = ctypes.c_int
         _lib = L
     return _lib
@@ -115,14 +118,14 @@ def order(L: int, seed: int, sample: int) -> np.ndarray:
 
 
 def sweep_order(L: int, mask: int, order_arr, smax: bool = False, check: bool = False,
-                run_to_end: bool = False):
+                run_to_end: bool = False, periodic: bool = False):
     """Sweep over an explicit order; returns (nstar, mass[, smax array])."""
     o = np.ascontiguousarray(order_arr, dtype=np.uint32)
     ns = np.zeros(1, dtype=np.int32)
     ms = np.zeros(1, dtype=np.int32)
     sm = np.zeros(max(len(o), 1), dtype=np.int32) if smax else None
-    rc = lib().nzo_sweep_order(L, mask, _ptr(o), len(o), _ptr(ns), _ptr(ms),
-                               _ptr(sm) if smax else None, int(check), int(run_to_end))
+    rc = lib().nzo_sweep_order_bc(L, mask, int(periodic), _ptr(o), len(o), _ptr(ns), _ptr(ms),
+                                  _ptr(sm) if smax else None, int(check), int(run_to_end))
     if rc == -2:
         raise AssertionError("oracle invariant violated")
     _check(rc, "sweep_order")
@@ -168,13 +171,14 @@ def convolve_window(Q, n_lo: int, N: int, p_grid):
     return out, cov
 
 
-def smax_window(L: int, mask: int, seed: int, sample0: int, nsamples: int, n_lo: int, n_hi: int) -> np.ndarray:
+def smax_window(L: int, mask: int, seed: int, sample0: int, nsamples: int, n_lo: int, n_hi: int,
+                periodic: bool = False) -> np.ndarray:
     """Sum over samples sample0 .. of S_max(n), n in [n_lo, n_hi) (the largest
     cluster size after n occupied sites), from the serial sweep run past n*."""
     acc = np.zeros(n_hi - n_lo, dtype=np.int64)
     for s in range(sample0, sample0 + nsamples):
         o = order(L, seed, s)
-        _, _, sm = sweep_order(L, mask, o[:n_hi], smax=True, run_to_end=True)
+        _, _, sm = sweep_order(L, mask, o[:n_hi], smax=True, run_to_end=True, periodic=periodic)
         acc += sm[n_lo - 1:n_hi - 1]
     return acc
 

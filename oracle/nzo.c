@@ -202,13 +202,15 @@ static void decode(int32_t L, int64_t i, int32_t x[5])
     }
 }
 
-/* Neighbour t of s along offset d, or -1 when it falls outside the lattice. */
-static int64_t neighbour(int32_t L, const int32_t xs[5], const int32_t *d)
+/* Neighbour t of s along offset d: free boundaries give -1 when it falls
+ * outside the lattice; periodic boundaries take every coordinate mod L. */
+static int64_t neighbour(int32_t L, const int32_t xs[5], const int32_t *d, int periodic)
 {
     int64_t t = 0, stride = 1;
     for (int j = 0; j < 5; ++j) {
         int32_t y = xs[j] + d[j];
-        if (y < 0 || y >= L) return -1;
+        if (periodic) y = ((y % L) + L) % L;
+        else if (y < 0 || y >= L) return -1;
         t += stride * y;
         stride *= L;
     }
@@ -217,6 +219,12 @@ static int64_t neighbour(int32_t L, const int32_t xs[5], const int32_t *d)
 
 int nzo_sweep_order(int32_t L, uint32_t mask, const uint32_t *order, int64_t n_order,
                     int32_t *nstar, int32_t *mass, int32_t *smax, int check, int run_to_end)
+{
+    return nzo_sweep_order_bc(L, mask, 0, order, n_order, nstar, mass, smax, check, run_to_end);
+}
+
+int nzo_sweep_order_bc(int32_t L, uint32_t mask, int periodic, const uint32_t *order, int64_t n_order,
+                       int32_t *nstar, int32_t *mass, int32_t *smax, int check, int run_to_end)
 {
     if (L < 1 || L > 55 || mask < 1 || mask > 127 || !order || !nstar || !mass) return -1;
     int64_t N = ipow5(L);
@@ -240,11 +248,12 @@ int nzo_sweep_order(int32_t L, uint32_t mask, const uint32_t *order, int64_t n_o
         int32_t xs[5];
         decode(L, s, xs);
         ptr[s] = -1;
-        flags[s] = (uint8_t)((xs[0] == 0 ? FLAG_LO : 0) | (xs[0] == L - 1 ? FLAG_HI : 0));
+        /* periodic boundaries have no borders: nothing spans */
+        flags[s] = periodic ? 0 : (uint8_t)((xs[0] == 0 ? FLAG_LO : 0) | (xs[0] == L - 1 ? FLAG_HI : 0));
         if (biggest < 1) biggest = 1;
 
         for (int q = 0; q < z; ++q) {
-            int64_t t = neighbour(L, xs, off + 5 * q);
+            int64_t t = neighbour(L, xs, off + 5 * q, periodic);
             if (t < 0 || ptr[t] == EMPTY) continue;
             int32_t rs = uf_find(ptr, s);
             int32_t rt = uf_find(ptr, (int32_t)t);
@@ -375,7 +384,7 @@ int nzo_prefix_labels(int32_t L, uint32_t mask, const uint32_t *order, int64_t n
         decode(L, s, xs);
         ptr[s] = -1;
         for (int q = 0; q < z; ++q) {
-            int64_t t = neighbour(L, xs, off + 5 * q);
+            int64_t t = neighbour(L, xs, off + 5 * q, 0);
             if (t < 0 || ptr[t] == EMPTY) continue;
             int32_t rs = uf_find(ptr, s), rt = uf_find(ptr, (int32_t)t);
             if (rs != rt) uf_union(ptr, flags, rs, rt);

@@ -66,6 +66,12 @@ int nzo_order(int32_t L, uint64_t seed, uint64_t sample, uint32_t *order);
 int nzo_sweep_order(int32_t L, uint32_t mask, const uint32_t *order, int64_t n_order,
                     int32_t *nstar, int32_t *mass, int32_t *smax, int check, int run_to_end);
 
+/* The same with a boundary choice: periodic != 0 wraps every coordinate mod L
+ * (the neighbourhood of a site then always has z members; there are no
+ * borders, so nothing spans and nstar = mass = 0). */
+int nzo_sweep_order_bc(int32_t L, uint32_t mask, int periodic, const uint32_t *order, int64_t n_order,
+                       int32_t *nstar, int32_t *mass, int32_t *smax, int check, int run_to_end);
+
 /* Convenience: keys, sort and sweep for one sample. */
 int nzo_sweep(int32_t L, uint32_t mask, uint64_t seed, uint64_t sample,
               int32_t *nstar, int32_t *mass);

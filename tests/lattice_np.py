@@ -22,9 +22,10 @@ def coords(L, sites):
     return np.stack([(sites // L**j) % L for j in range(5)], axis=-1)
 
 
-def components(L, mask, occupied_sites):
+def components(L, mask, occupied_sites, periodic=False):
     """Labels (smallest member index; -1 for empty) of the clusters formed by the
-    occupied sites under the zone-mask neighbourhood with free boundaries."""
+    occupied sites under the zone-mask neighbourhood with free (or periodic:
+    coordinates mod L) boundaries."""
     N = L**5
     occ = np.zeros(N, dtype=bool)
     occ[np.asarray(occupied_sites, dtype=np.int64)] = True
@@ -33,6 +34,8 @@ def components(L, mask, occupied_sites):
     rows, cols = [], []
     for d in shell_offsets(mask):
         y = x + d
+        if periodic:
+            y = np.mod(y, L)
         inb = ((y >= 0) & (y < L)).all(axis=1)
         t = (y[inb] * (L ** np.arange(5))).sum(axis=1)
         ok = occ[t]

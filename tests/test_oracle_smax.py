@@ -62,3 +62,35 @@ def test_window_coverage_is_binomial_mass(nzo):
     _, cov = nzo.convolve_window(np.zeros(hi - lo), lo, N, p)
     want = stats.binom.cdf(hi - 1, N, p) - stats.binom.cdf(lo - 1, N, p)
     assert np.allclose(cov, want, atol=1e-10)
+
+
+@pytest.mark.parametrize("L,mask,sample", [(5, 0x01, 0), (5, 0x7F, 1), (6, 0x06, 2)])
+def test_periodic_smax_matches_connected_components(nzo, L, mask, sample):
+    N = L**5
+    o = nzo.order(L, 31, sample)
+    ns, ms, sm = nzo.sweep_order(L, mask, o, smax=True, run_to_end=True, periodic=True)
+    assert ns == 0 and ms == 0   # no borders: nothing spans
+    for n in sorted({1, N // 20, N // 8, N // 4, N // 2, N}):
+        lab = lattice_np.components(L, mask, o[:n], periodic=True)
+        assert sm[n - 1] == int(np.bincount(lab[lab >= 0]).max()), n
+    assert sm[-1] == N
+
+
+def test_periodic_translation_invariance(nzo):
+    """Translating every site by a fixed vector (mod L) maps a periodic lattice
+    onto itself, so the largest-cluster track of the translated order is the
+    same; with free boundaries it is not."""
+    L, mask = 5, 0x03
+    N = L**5
+    o = nzo.order(L, 8, 3)
+    x = lattice_np.coords(L, o)
+    c = np.array([2, 0, 4, 1, 3])
+    t = (np.mod(x + c, L) * (L ** np.arange(5))).sum(axis=1).astype(np.uint32)
+    _, _, a = nzo.sweep_order(L, mask, o, smax=True, run_to_end=True, periodic=True)
+    _, _, b = nzo.sweep_order(L, mask, t, smax=True, run_to_end=True, periodic=True)
+    assert (a == b).all()
+    _, _, fa = nzo.sweep_order(L, mask, o, smax=True, run_to_end=True)
+    _, _, fb = nzo.sweep_order(L, mask, t, smax=True, run_to_end=True)
+    assert not (fa == fb).all()
+    # every site has its full neighbourhood: a sweep of all N sites merges to one cluster
+    assert a[-1] == N
