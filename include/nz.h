@@ -7,7 +7,8 @@
  * neighborhoods in five dimension"):
  *   - Sec. I: sites of an L^5 lattice are occupied at random; a cluster that
  *     connects opposite borders "spans"; here the borders are the faces
- *     x0 = 0 and x0 = L-1 and boundaries are free (no wrapping);
+ *     x0 = 0 and x0 = L-1 and boundaries are free (no wrapping) for every
+ *     first-spanning call; the largest-cluster call also takes periodic ones;
  *   - Sec. II.A.2, eqs. (7)-(8), Table I: a neighbourhood is any non-empty set
  *     of coordination zones 1..7, zone k being the shell r^2 = k (10, 40, 80,
  *     90, 112, 240, 320 sites); bit k-1 of zone_mask selects zone k;
@@ -47,7 +48,10 @@ extern "C" {
 #define NZ_EDEVICE (-4)       /* a HIP runtime call or kernel launch failed */
 #define NZ_EWORKSPACE (-5)    /* the caller's workspace is too small */
 
-#define NZ_FREE 0             /* free boundaries: the only boundary implemented */
+#define NZ_FREE 0             /* free boundaries */
+#define NZ_PERIODIC 1         /* periodic boundaries (coordinates mod L, L >= 5): no borders, so no
+                                 spanning test; accepted by nz_smax_window only (the first-spanning
+                                 entry points return NZ_EUNSUPPORTED) */
 
 /* Message describing the last failure on the calling thread (never NULL). */
 const char *nz_last_error(void);
@@ -63,7 +67,8 @@ int nz_coordination(uint32_t zone_mask);
 /*
  * nz_sweep -- n* and spanning mass of samples 0 .. nsamples-1 (Sec. II.B).
  *   L          lattice side, 1 <= L <= 55 (N = L^5 < 2^29);
- *   zone_mask  1..127;  boundary  NZ_FREE;  seed  any 64-bit value;
+ *   zone_mask  1..127;  boundary  NZ_FREE (NZ_PERIODIC: NZ_EUNSUPPORTED);
+ *   seed  any 64-bit value;
  *   nstar      HOST array of nsamples int32, written;
  *   mass       HOST array of nsamples int32, written; may be NULL.
  * Synchronous; allocates and frees its own device memory; runs on the current
@@ -88,6 +93,7 @@ int nz_canonical(const uint64_t *hist, int64_t hist_len, const double *p_grid, i
  * over samples sample0 .. sample0+nsamples-1, for n in [n_lo, n_hi): the
  * observable of eqs. (5)-(6) (P_max = S_max / L^5 before the convolution).
  * The sweep runs on past n* through the window, one site per step.
+ *   boundary   NZ_FREE or NZ_PERIODIC (L >= 5);
  *   n0         -1: plain sweep; else 0 <= n0 < n_lo: the sites of rank < n0
  *              (keys below floor(n0 / N * 2^64)) are labelled in bulk first
  *              (if that count reaches the window, n0 is halved and the sample

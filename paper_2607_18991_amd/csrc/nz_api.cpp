@@ -292,7 +292,10 @@ int check_job(const nz_job &j, int idx)
 {
     if (j.L < 1 || j.L > 55) return fail(j.L < 1 ? NZ_EINVAL : NZ_EUNSUPPORTED, "job %d: L = %d outside [1, 55]", idx, j.L);
     if (j.zone_mask < 1 || j.zone_mask > 127) return fail(NZ_EINVAL, "job %d: zone_mask %u outside [1, 127]", idx, j.zone_mask);
-    if (j.boundary != NZ_FREE) return fail(NZ_EUNSUPPORTED, "job %d: only free boundaries (NZ_FREE) are implemented", idx);
+    if (j.boundary != NZ_FREE && j.boundary != NZ_PERIODIC)
+        return fail(NZ_EINVAL, "job %d: boundary %d is neither NZ_FREE nor NZ_PERIODIC", idx, j.boundary);
+    if (j.boundary == NZ_PERIODIC && j.L < 5)
+        return fail(NZ_EUNSUPPORTED, "job %d: periodic boundaries need L >= 5", idx);
     if (j.nsamples < 0) return fail(NZ_EINVAL, "job %d: nsamples < 0", idx);
     if (j.sample0 < 0) return fail(NZ_EINVAL, "job %d: sample0 < 0", idx);
     const int64_t N = pow5(j.L);
@@ -490,6 +493,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 d.smax_mode = p.win_hi > 0 ? 1 : 0;
                 d.win_lo = static_cast<int32_t>(p.win_lo);
                 d.win_hi = static_cast<int32_t>(p.win_hi);
+                d.periodic = J.boundary == NZ_PERIODIC ? 1 : 0;
                 out_index[di] = p.out;
                 chunk_of_desc[di] = ci;
                 desc_of_chunk[ci] = di;
@@ -802,6 +806,10 @@ NZ_API int nz_sweep_batch(const nz_job *jobs, int32_t njobs, void *d_ws, size_t 
         total += jobs[j].nsamples;
     }
     if (total == 0) return NZ_OK;
+    for (int j = 0; j < njobs; ++j)
+        if (jobs[j].boundary == NZ_PERIODIC)
+            return fail(NZ_EUNSUPPORTED, "job %d: first spanning on a periodic lattice (wrapping) is not implemented; "
+                                         "periodic boundaries serve nz_smax_window", j);
     if (!d_ws || !d_nstar) return fail(NZ_EINVAL, "workspace or n* output is NULL");
     if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(NZ_EINVAL, "workspace must be 256-byte aligned");
     Tune t;
@@ -843,6 +851,9 @@ NZ_API int nz_sweep(int32_t L, uint32_t zone_mask, int32_t boundary, int64_t nsa
     j.nsamples = nsamples;
     j.n0 = -1;
     if (int rc = check_job(j, 0)) return rc;
+    if (boundary == NZ_PERIODIC)
+        return fail(NZ_EUNSUPPORTED, "first spanning on a periodic lattice (wrapping) is not implemented; "
+                                     "periodic boundaries serve nz_smax_window");
     if (nsamples == 0) return NZ_OK;
     if (!nstar) return fail(NZ_EINVAL, "nstar is NULL");
     if (nsamples > 0x7FFFFFFF) return fail(NZ_EINVAL, "nsamples too large");

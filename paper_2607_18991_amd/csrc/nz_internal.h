@@ -59,6 +59,8 @@ struct NzSample {
     uint64_t off_win;     // smax mode: S_max(n) for n in [win_lo, win_hi), uint32 each
     int32_t win_lo;
     int32_t win_hi;
+    int32_t periodic;     // 1: coordinates wrap mod L (L >= 5); no borders, so no border flags
+    int32_t pad;
 };
 
 // Per-sample result/state record written by the kernels.

@@ -89,6 +89,26 @@ __device__ __forceinline__ uint32_t allowed_axis(int32_t x, int32_t L)
     return hi >= lo ? ((2u << hi) - (1u << lo)) : 0u;
 }
 
+// Periodic boundaries: the index correction of an offset whose steps leave
+// the lattice on the axes of `out` (the offset's code bits outside the allowed
+// set): +L^(j+1) for a negative step that left through 0, -L^(j+1) for a
+// positive one past L-1 (one wrap suffices for L >= 5).
+__device__ __forceinline__ int32_t wrap_fix(uint32_t out, int32_t L)
+{
+    int32_t fix = 0, p = L;
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+        const uint32_t b = (out >> (5 * j)) & 31u;
+        fix += (b & 0x03u) ? p : 0;
+        fix -= (b & 0x18u) ? p : 0;
+        p *= L;
+    }
+    return fix;
+}
+
+// An offset code with bits above 25 marks a padding slot (no offset).
+constexpr uint32_t kCodeBits = 0x1FFFFFFu;
+
 // Relaxed wavefront-scope accesses: ordinary cached loads and stores that the
 // compiler neither merges nor elides.  They serve state private to one wave and
 // the cache-tolerant walks of the bulk connected components; links and counts
@@ -434,6 +454,7 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
     const int32_t L = d.L;
     const int32_t zh = d.z >> 1;
     const uint64_t magic = d.magic;
+    const bool periodic = d.periodic != 0;
     int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
     const uint32_t *occ = reinterpret_cast<const uint32_t *>(ws + d.off_occ);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
@@ -454,8 +475,10 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
                 o.stride = 0;
                 o.code = 0xFFFFFFFFu;
                 if (k0 + q < zh) o = tab[k0 + q];
-                t[q] = s + o.stride;
-                w[q] = (o.code & ~A) == 0u ? occ[static_cast<uint32_t>(t[q]) >> 5] : 0u;
+                const uint32_t out = o.code & ~A;
+                const bool ok = out == 0u || (periodic && (o.code & ~kCodeBits) == 0u);
+                t[q] = s + o.stride + (periodic && out ? wrap_fix(out, L) : 0);
+                w[q] = ok ? occ[static_cast<uint32_t>(t[q]) >> 5] : 0u;
             }
 #pragma unroll
             for (int q = 0; q < HOOK_UNROLL; ++q) {
@@ -513,7 +536,7 @@ __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__rest
             p = ld_w(&par[r]);
         }
         if (r == s) {
-            const uint32_t fl = border_flags(static_cast<uint32_t>(s), L, d.magic);
+            const uint32_t fl = d.periodic ? 0u : border_flags(static_cast<uint32_t>(s), L, d.magic);
             st_w(&par[s], static_cast<int32_t>(NZ_ROOT | fl | 1u));
             if (fl == NZ_FLAGS) state[sid].status = NZ_ST_BACKOFF;   // L = 1: one site spans
         } else {
@@ -548,7 +571,7 @@ __global__ __launch_bounds__(256) void nz_accum_kernel(const NzSample *__restric
         if (r >= 0) {
             uint32_t *root = reinterpret_cast<uint32_t *>(&par[r]);
             atomicAdd(root, 1u);
-            const uint32_t fl = border_flags(static_cast<uint32_t>(s), L, d.magic);
+            const uint32_t fl = d.periodic ? 0u : border_flags(static_cast<uint32_t>(s), L, d.magic);
             if (fl) {
                 const uint32_t old = atomicOr(root, fl);
                 if (((old | fl) & NZ_FLAGS) == NZ_FLAGS && !d.smax_mode) state[sid].status = NZ_ST_BACKOFF;
@@ -767,18 +790,20 @@ struct SiteStep {
 
     template <int RES>
     __device__ __forceinline__ void prepare(const SweepMem<RES> &m, uint32_t *lds, uint32_t pc, int32_t L,
-                                            const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH])
+                                            const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH],
+                                            bool periodic = false)
     {
         const int32_t x0 = pc & 63, x1 = (pc >> 6) & 63, x2 = (pc >> 12) & 63, x3 = (pc >> 18) & 63, x4 = pc >> 24;
         s = x0 + L * (x1 + L * (x2 + L * (x3 + L * x4)));
         const uint32_t A = allowed_axis(x0, L) | (allowed_axis(x1, L) << 5) | (allowed_axis(x2, L) << 10) |
                            (allowed_axis(x3, L) << 15) | (allowed_axis(x4, L) << 20);
-        fl = (x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u);
+        fl = periodic ? 0u : ((x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u));
         own = m.occ_ld(lds, static_cast<uint32_t>(s) >> 5);
 #pragma unroll
         for (int c = 0; c < NCH; ++c) {
-            inb[c] = (ocode[c] & ~A) == 0u;
-            tn[c] = s + ostride[c];
+            const uint32_t out = ocode[c] & ~A;
+            inb[c] = out == 0u || (periodic && (ocode[c] & ~kCodeBits) == 0u);
+            tn[c] = s + ostride[c] + (periodic && out ? wrap_fix(out, L) : 0);
             word[c] = inb[c] ? m.occ_ld(lds, static_cast<uint32_t>(tn[c]) >> 5) : 0u;
         }
     }
@@ -1170,6 +1195,7 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         // smax mode: the sweep runs on past n* and records the largest cluster
         // after every addition with win_lo <= r < win_hi
         const bool smax_mode = d.smax_mode != 0;
+        const bool periodic = d.periodic != 0;
         int32_t smax = a.state[sid].smax;
         uint32_t *win = reinterpret_cast<uint32_t *>(a.ws + d.off_win);
         // One addition done (r sites occupied, the new site's cluster has
@@ -1259,12 +1285,12 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         int got = bc.next(pc, lane);
         if (got < 0) status = NZ_ST_BUCKET;
         if constexpr (kLookahead<NCH>) {
-            if (got == 1) cur.prepare(m, lds, pc, L, ostride, ocode);
+            if (got == 1) cur.prepare(m, lds, pc, L, ostride, ocode, periodic);
             while (got == 1) {
                 ++r;
                 uint32_t pcn = 0;
                 const int gotn = bc.next(pcn, lane);
-                if (gotn == 1) nxt.prepare(m, lds, pcn, L, ostride, ocode);
+                if (gotn == 1) nxt.prepare(m, lds, pcn, L, ostride, ocode, periodic);
                 uint32_t total, flags;
                 sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
                 if (finished(total, flags)) break;
@@ -1278,7 +1304,7 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         } else {
             while (got == 1) {
                 ++r;
-                cur.prepare(m, lds, pc, L, ostride, ocode);
+                cur.prepare(m, lds, pc, L, ostride, ocode, periodic);
                 uint32_t total, flags;
                 sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
                 if (finished(total, flags)) break;

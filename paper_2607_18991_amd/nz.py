@@ -21,6 +21,7 @@ NZ_ENOMEM = -3
 NZ_EDEVICE = -4
 NZ_EWORKSPACE = -5
 NZ_FREE = 0
+NZ_PERIODIC = 1
 NZ_MLP_NPARAM = 8 * 64 + 64 + 64 * 64 + 64 + 64 * 2 + 2
 NZ_MLP_NACT = 128
 

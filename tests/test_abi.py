@@ -108,3 +108,16 @@ def test_smax_window_validation():
     with pytest.raises(nz.NzError) as e:
         nz.nz_convolve_window(np.ones(3), 5, 4, [0.5])
     assert e.value.code == nz.NZ_EINVAL
+
+
+def test_boundary_codes():
+    # periodic boundaries serve the largest-cluster call only, for L >= 5
+    with pytest.raises(nz.NzError) as e:
+        nz.nz_sweep(6, 1, 4, 1, boundary=nz.NZ_PERIODIC)
+    assert e.value.code == nz.NZ_EUNSUPPORTED
+    with pytest.raises(nz.NzError) as e:
+        nz.nz_sweep(6, 1, 4, 1, boundary=2)
+    assert e.value.code == nz.NZ_EINVAL
+    with pytest.raises(nz.NzError) as e:
+        nz.nz_smax_window(4, 1, 1, 0, 2, 10, 20, boundary=nz.NZ_PERIODIC)
+    assert e.value.code == nz.NZ_EUNSUPPORTED

@@ -51,3 +51,21 @@ def test_pmax_convolution_on_gpu_sums():
     b, cb = oracle.convolve_window(want, lo, N, p)
     assert np.allclose(a, b, rtol=1e-12) and np.allclose(ca, cb, atol=1e-12)
     assert (ca[2:5] > 0.999).all()
+
+
+@pytest.mark.parametrize("L,mask,seed,ns,lo,hi,n0", [
+    (5, 0x01, 31, 24, 200, 700, -1),
+    (6, 0x7F, 32, 16, 5, 300, -1),
+    (6, 0x01, 33, 16, 900, 1500, 600),
+    (8, 0x03, 34, 8, 900, 1600, 700),
+    (7, 0x1C, 35, 12, 60, 500, 30),
+])
+def test_periodic_smax_window_matches_oracle(L, mask, seed, ns, lo, hi, n0):
+    import oracle
+    from paper_2607_18991_amd import nz
+
+    got = nz.nz_smax_window(L, mask, seed, 0, ns, lo, hi, n0=n0, boundary=nz.NZ_PERIODIC)
+    want = oracle.smax_window(L, mask, seed, 0, ns, lo, hi, periodic=True)
+    assert (got.astype(np.int64) == want).all()
+    free = oracle.smax_window(L, mask, seed, 0, ns, lo, hi)
+    assert not (free == want).all()   # the boundaries do matter here
