@@ -39,7 +39,7 @@ def window_for(L: int, p_lo: float, p_hi: float, k: float = 6.0):
     return max(1, int(math.floor(lo))), min(N, int(math.ceil(hi)) + 1)
 
 
-def pmax_curve(L: int, mask: int, seed: int, samples: int, p_grid, prefill: bool = True):
+def pmax_curve(L: int, mask: int, seed: int, samples: int, p_grid, prefill: bool = True, boundary: int = nz.NZ_FREE):
     """P_max(p; L) on p_grid, the binomial mass the window covers at each p,
     and the GPU time of the window sweep."""
     p_grid = np.asarray(p_grid, dtype=np.float64)
@@ -49,7 +49,7 @@ def pmax_curve(L: int, mask: int, seed: int, samples: int, p_grid, prefill: bool
     # fluctuation of the count of keys under the threshold)
     n0 = int(lo * 0.98) if prefill and lo > 64 else -1
     t0 = time.perf_counter()
-    sums = nz.nz_smax_window(L, mask, seed, 0, samples, lo, hi, n0=n0)
+    sums = nz.nz_smax_window(L, mask, seed, 0, samples, lo, hi, n0=n0, boundary=boundary)
     secs = time.perf_counter() - t0
     Q = sums.astype(np.float64) / (samples * N)
     P, cover = nz.nz_convolve_window(Q, lo, N, p_grid)
@@ -68,12 +68,13 @@ def crossing(p, ya, yb):
     return float(p[i] - d[i] * (p[i + 1] - p[i]) / (d[i + 1] - d[i]))
 
 
-def estimate(mask: int, Ls, samples, p_grid, seed: int = 0xF55, beta_over_nu: float = BETA5 / NU5_FSS):
+def estimate(mask: int, Ls, samples, p_grid, seed: int = 0xF55, beta_over_nu: float = BETA5 / NU5_FSS,
+             boundary: int = nz.NZ_FREE):
     """Rescaled curves for every L and the crossings of successive L."""
     p_grid = np.asarray(p_grid, dtype=np.float64)
     curves, runs = {}, []
     for L, S in zip(Ls, samples):
-        P, cover, info = pmax_curve(L, mask, seed + L, S, p_grid)
+        P, cover, info = pmax_curve(L, mask, seed + L, S, p_grid, boundary=boundary)
         if cover.min() < 1 - 1e-6:
             raise RuntimeError(f"window of L={L} misses binomial mass {1 - cover.min():.2e}")
         curves[L] = P * L**beta_over_nu
@@ -82,28 +83,28 @@ def estimate(mask: int, Ls, samples, p_grid, seed: int = 0xF55, beta_over_nu: fl
     for a, b in zip(Ls, Ls[1:]):
         pairs.append({"L": [a, b], "p": crossing(p_grid, curves[a], curves[b])})
     found = [c["p"] for c in pairs if c["p"] is not None]
-    return {"mask": mask, "beta_over_nu": beta_over_nu, "crossings": pairs,
+    return {"mask": mask, "boundary": boundary, "beta_over_nu": beta_over_nu, "crossings": pairs,
             "p_c": float(np.mean(found)) if found else None,
             "spread": float(np.std(found)) if len(found) > 1 else None,
             "runs": runs, "p_grid": p_grid.tolist(), "curves": {str(L): c.tolist() for L, c in curves.items()}}
 
 
-def smax_at(L: int, mask: int, p: float, samples: int, seed: int):
+def smax_at(L: int, mask: int, p: float, samples: int, seed: int, boundary: int = nz.NZ_FREE):
     """<S_max>(p; L): the window of n around p*N holding the binomial mass of p,
     convolved at p and multiplied by N."""
-    P, cover, info = pmax_curve(L, mask, seed, samples, [p])
+    P, cover, info = pmax_curve(L, mask, seed, samples, [p], boundary=boundary)
     if cover[0] < 1 - 1e-6:
         raise RuntimeError(f"window of L={L} misses binomial mass {1 - cover[0]:.2e}")
     return float(P[0]) * L**5, info
 
 
-def df_estimate(mask: int, p_c: float, Ls, samples, seed: int = 0xDF5):
+def df_estimate(mask: int, p_c: float, Ls, samples, seed: int = 0xDF5, boundary: int = nz.NZ_FREE):
     """Fractal dimension of the incipient cluster (Sec. II.A.4, Sec. III.B):
     the least-squares slope of ln <S_max(p_c)> against ln L, with its standard
     error from the fit residuals."""
     pts, runs = [], []
     for L, S in zip(Ls, samples):
-        m, info = smax_at(L, mask, p_c, S, seed + L)
+        m, info = smax_at(L, mask, p_c, S, seed + L, boundary)
         pts.append((math.log(L), math.log(m)))
         runs.append(dict(info, smax=m))
     x = np.array([a for a, _ in pts])
@@ -113,7 +114,7 @@ def df_estimate(mask: int, p_c: float, Ls, samples, seed: int = 0xDF5):
     dof = max(1, len(x) - 2)
     sigma2 = float(res[0]) / dof if len(res) else 0.0
     se = math.sqrt(sigma2 / float(((x - x.mean()) ** 2).sum())) if len(x) > 2 else None
-    return {"mask": mask, "p_c": p_c, "d_f": float(coef[0]), "d_f_stderr": se, "runs": runs}
+    return {"mask": mask, "boundary": boundary, "p_c": p_c, "d_f": float(coef[0]), "d_f_stderr": se, "runs": runs}
 
 
 def main():
@@ -125,15 +126,17 @@ def main():
     ap.add_argument("--seed", type=lambda s: int(s, 0), default=0xF55)
     ap.add_argument("--df", type=float, default=None, metavar="P_C",
                     help="fit the fractal dimension at this threshold instead of locating the crossing")
+    ap.add_argument("--periodic", action="store_true", help="periodic boundaries (default: free)")
     args = ap.parse_args()
     import torch
 
     torch.cuda.set_device(0)
+    bc = nz.NZ_PERIODIC if args.periodic else nz.NZ_FREE
     if args.df is not None:
-        print(json.dumps(df_estimate(args.mask, args.df, args.L, args.samples, args.seed)), flush=True)
+        print(json.dumps(df_estimate(args.mask, args.df, args.L, args.samples, args.seed, bc)), flush=True)
         return
     p = np.arange(args.p[0], args.p[1] + args.p[2] / 2, args.p[2])
-    res = estimate(args.mask, args.L, args.samples, p, args.seed)
+    res = estimate(args.mask, args.L, args.samples, p, args.seed, boundary=bc)
     res.pop("curves")
     res.pop("p_grid")
     print(json.dumps(res), flush=True)
