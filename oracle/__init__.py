@@ -57,6 +57,8 @@ def lib():
         L.nzo_sweep.restype = ctypes.c_int
         L.nzo_sweep_many.argtypes = [i32, u32, u64, u64, i64, ctypes.c_int, P, P, P]
         L.nzo_sweep_many.restype = ctypes.c_int
+        L.nzo_sweep_many_bc.argtypes = [i32, u32, ctypes.c_int, u64, u64, i64, ctypes.c_int, P, P, P]
+        L.nzo_sweep_many_bc.restype = ctypes.c_int
         L.nzo_prefix_labels.argtypes = [i32, u32, P, i64, P]
         L.nzo_prefix_labels.restype = ctypes.c_int
         L.nzo_canonical.argtypes = [P, i64, P, i64, P]
@@ -142,12 +144,14 @@ def sweep(L: int, mask: int, seed: int, sample: int):
 
 
 def sweep_many(L: int, mask: int, seed: int, sample0: int, count: int, nthreads: int = 1,
-               times: bool = False):
+               times: bool = False, periodic: bool = False):
+    """n* and mass of samples sample0 .. sample0+count-1; periodic: the first
+    cluster that wraps around axis 0 (L >= 5)."""
     ns = np.zeros(count, dtype=np.int32)
     ms = np.zeros(count, dtype=np.int32)
     tm = np.zeros(3, dtype=np.float64)
-    _check(lib().nzo_sweep_many(L, mask, seed, sample0, count, nthreads, _ptr(ns), _ptr(ms),
-                                _ptr(tm)), "sweep_many")
+    _check(lib().nzo_sweep_many_bc(L, mask, int(periodic), seed, sample0, count, nthreads, _ptr(ns), _ptr(ms),
+                                   _ptr(tm)), "sweep_many")
     if times:
         return ns, ms, tm
     return ns, ms

@@ -164,7 +164,15 @@ int nzo_order(int32_t L, uint64_t seed, uint64_t sample, uint32_t *order)
  * unoccupied site, the parent index for a non-root, and minus the cluster size
  * for a root.  Finds compress the whole path; unions attach the smaller
  * cluster below the larger one (equal sizes: the smaller index stays root).
- * flags[root] holds LO (a member has x0 = 0) and HI (a member has x0 = L-1). */
+ * flags[root] holds LO (a member has x0 = 0) and HI (a member has x0 = L-1).
+ *
+ * Periodic boundaries (Newman & Ziff 2001, Sec. III, wrapping clusters): every
+ * site also keeps dx[i], its x0 displacement from its parent in the unwrapped
+ * lattice (0 at a root), so the displacement of a site from its root is the
+ * sum along its path.  An edge s -> t = s + d inside one cluster closes a loop;
+ * the loop winds around axis 0 exactly when D(s) + d0 != D(t), and the cluster
+ * is then marked LO | HI, the same state a spanning cluster has under free
+ * boundaries. */
 
 #define EMPTY INT32_MIN
 #define FLAG_LO 1u
@@ -177,6 +185,27 @@ static int32_t uf_find(int32_t *ptr, int32_t i)
     while (ptr[i] >= 0) {
         int32_t next = ptr[i];
         ptr[i] = r;
+        i = next;
+    }
+    return r;
+}
+
+/* Root of i and, through *disp, the x0 displacement of i from it; the path is
+ * compressed with each node's displacement rewritten to be from the root. */
+static int32_t uf_find_disp(int32_t *ptr, int32_t *dx, int32_t i, int32_t *disp)
+{
+    int32_t r = i, total = 0;
+    while (ptr[r] >= 0) {
+        total += dx[r];
+        r = ptr[r];
+    }
+    *disp = total;
+    int32_t rem = total;
+    while (ptr[i] >= 0) {
+        int32_t next = ptr[i], step = dx[i];
+        ptr[i] = r;
+        dx[i] = rem;
+        rem -= step;
         i = next;
     }
     return r;
@@ -233,9 +262,14 @@ int nzo_sweep_order_bc(int32_t L, uint32_t mask, int periodic, const uint32_t *o
     int32_t off[892 * 5];
     int z = nzo_offsets(mask, off);
 
+    /* below L = 5 two offsets of one neighbourhood can reach the same site
+     * around the torus, and a displacement is no longer fixed by the pair */
+    if (periodic && L < 5) return -1;
+
     int32_t *ptr = (int32_t *)malloc((size_t)N * sizeof(int32_t));
     uint8_t *flags = (uint8_t *)calloc((size_t)N, 1);
-    if (!ptr || !flags) { free(ptr); free(flags); return -1; }
+    int32_t *dx = periodic ? (int32_t *)calloc((size_t)N, sizeof(int32_t)) : NULL;
+    if (!ptr || !flags || (periodic && !dx)) { free(ptr); free(flags); free(dx); return -1; }
     for (int64_t i = 0; i < N; ++i) ptr[i] = EMPTY;
 
     *nstar = 0;
@@ -248,20 +282,39 @@ int nzo_sweep_order_bc(int32_t L, uint32_t mask, int periodic, const uint32_t *o
         int32_t xs[5];
         decode(L, s, xs);
         ptr[s] = -1;
-        /* periodic boundaries have no borders: nothing spans */
+        /* periodic boundaries have no borders; a cluster there "spans" when it
+         * wraps around axis 0 */
         flags[s] = periodic ? 0 : (uint8_t)((xs[0] == 0 ? FLAG_LO : 0) | (xs[0] == L - 1 ? FLAG_HI : 0));
         if (biggest < 1) biggest = 1;
 
         for (int q = 0; q < z; ++q) {
             int64_t t = neighbour(L, xs, off + 5 * q, periodic);
             if (t < 0 || ptr[t] == EMPTY) continue;
-            int32_t rs = uf_find(ptr, s);
-            int32_t rt = uf_find(ptr, (int32_t)t);
-            if (rs != rt) {
-                int32_t r = uf_union(ptr, flags, rs, rt);
-                ++unions;
-                if (-ptr[r] > biggest) biggest = -ptr[r];
+            if (!periodic) {
+                int32_t rs = uf_find(ptr, s);
+                int32_t rt = uf_find(ptr, (int32_t)t);
+                if (rs != rt) {
+                    int32_t r = uf_union(ptr, flags, rs, rt);
+                    ++unions;
+                    if (-ptr[r] > biggest) biggest = -ptr[r];
+                }
+                continue;
             }
+            /* unwrapped: t = s + d, so its x0 is that of s plus d0 */
+            int32_t d0 = off[5 * q], Ds, Dt;
+            int32_t rs = uf_find_disp(ptr, dx, s, &Ds);
+            int32_t rt = uf_find_disp(ptr, dx, (int32_t)t, &Dt);
+            if (rs == rt) {
+                if (Ds + d0 != Dt) flags[rs] |= FLAG_LO | FLAG_HI;
+                continue;
+            }
+            int32_t r = uf_union(ptr, flags, rs, rt);
+            /* the attached root's displacement from the survivor, from
+             * x0(rs) = x0(s) - Ds and x0(rt) = x0(s) + d0 - Dt */
+            if (r == rt) dx[rs] = Dt - d0 - Ds;
+            else dx[rt] = Ds + d0 - Dt;
+            ++unions;
+            if (-ptr[r] > biggest) biggest = -ptr[r];
         }
 
         if (smax) smax[k] = biggest;
@@ -276,7 +329,8 @@ int nzo_sweep_order_bc(int32_t L, uint32_t mask, int periodic, const uint32_t *o
             if (sum != k + 1 || roots != k + 1 - unions) { rc = -2; break; }
         }
 
-        int32_t r = uf_find(ptr, s);
+        int32_t dummy;
+        int32_t r = periodic ? uf_find_disp(ptr, dx, s, &dummy) : uf_find(ptr, s);
         if (*nstar == 0 && flags[r] == (FLAG_LO | FLAG_HI)) {
             *nstar = (int32_t)(k + 1);
             *mass = -ptr[r];
@@ -285,6 +339,7 @@ int nzo_sweep_order_bc(int32_t L, uint32_t mask, int periodic, const uint32_t *o
     }
     free(ptr);
     free(flags);
+    free(dx);
     return rc;
 }
 
@@ -308,6 +363,7 @@ int nzo_sweep(int32_t L, uint32_t mask, uint64_t seed, uint64_t sample,
 typedef struct {
     int32_t L;
     uint32_t mask;
+    int periodic;
     uint64_t seed, sample0;
     int64_t count;
     int64_t next;            /* shared work counter */
@@ -330,7 +386,7 @@ static void *many_worker(void *arg)
         rc = order_timed(c->L, c->seed, c->sample0 + (uint64_t)k, order, &tk, &ts);
         if (rc) break;
         double t0 = now_s();
-        rc = nzo_sweep_order(c->L, c->mask, order, N, &c->nstar[k], &c->mass[k], NULL, 0, 0);
+        rc = nzo_sweep_order_bc(c->L, c->mask, c->periodic, order, N, &c->nstar[k], &c->mass[k], NULL, 0, 0);
         tw += now_s() - t0;
     }
     free(order);
@@ -347,11 +403,18 @@ int nzo_sweep_many(int32_t L, uint32_t mask, uint64_t seed, uint64_t sample0,
                    int64_t count, int nthreads, int32_t *nstar, int32_t *mass,
                    double times[3])
 {
+    return nzo_sweep_many_bc(L, mask, 0, seed, sample0, count, nthreads, nstar, mass, times);
+}
+
+int nzo_sweep_many_bc(int32_t L, uint32_t mask, int periodic, uint64_t seed, uint64_t sample0,
+                      int64_t count, int nthreads, int32_t *nstar, int32_t *mass, double times[3])
+{
     if (L < 1 || L > 55 || mask < 1 || mask > 127 || count < 0 || nthreads < 1) return -1;
+    if (periodic && L < 5) return -1;
     if (count > 0 && (!nstar || !mass)) return -1;
     many_ctx c;
     memset(&c, 0, sizeof c);
-    c.L = L; c.mask = mask; c.seed = seed; c.sample0 = sample0; c.count = count;
+    c.L = L; c.mask = mask; c.periodic = periodic; c.seed = seed; c.sample0 = sample0; c.count = count;
     c.nstar = nstar; c.mass = mass;
     pthread_mutex_init(&c.lock, NULL);
     pthread_t *th = (pthread_t *)malloc((size_t)nthreads * sizeof(pthread_t));

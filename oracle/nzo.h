@@ -21,6 +21,10 @@
  *     K(i) (Salmon, Moraes, Dror & Shaw, SC'11), ties broken by site index;
  *   - n* is the first n at which some cluster of the first n sites contains a
  *     site with x0 = 0 and a site with x0 = L-1; mass is that cluster's size;
+ *   - periodic boundaries (L >= 5): every coordinate is taken mod L, and n* is
+ *     the first n at which some cluster wraps around axis 0, i.e. holds a loop
+ *     whose unwrapped x0 displacement is a non-zero multiple of L (Newman &
+ *     Ziff 2001, Sec. III); mass is that cluster's size;
  *   - R_L(p) = sum_n C(N,n) p^n (1-p)^(N-n) F_n, the binomial convolution of
  *     Sec. II.B, with F_n the fraction of samples with 1 <= n* <= n.
  */
@@ -67,8 +71,9 @@ int nzo_sweep_order(int32_t L, uint32_t mask, const uint32_t *order, int64_t n_o
                     int32_t *nstar, int32_t *mass, int32_t *smax, int check, int run_to_end);
 
 /* The same with a boundary choice: periodic != 0 wraps every coordinate mod L
- * (the neighbourhood of a site then always has z members; there are no
- * borders, so nothing spans and nstar = mass = 0). */
+ * (the neighbourhood of a site then always has z members) and n*, mass refer
+ * to the first cluster that wraps around axis 0, found from the x0
+ * displacement of every site from its parent.  Periodic needs L >= 5. */
 int nzo_sweep_order_bc(int32_t L, uint32_t mask, int periodic, const uint32_t *order, int64_t n_order,
                        int32_t *nstar, int32_t *mass, int32_t *smax, int check, int run_to_end);
 
@@ -82,6 +87,10 @@ int nzo_sweep(int32_t L, uint32_t mask, uint64_t seed, uint64_t sample,
 int nzo_sweep_many(int32_t L, uint32_t mask, uint64_t seed, uint64_t sample0,
                    int64_t count, int nthreads, int32_t *nstar, int32_t *mass,
                    double times[3]);
+
+/* The same with a boundary choice (periodic != 0: first wrap around axis 0). */
+int nzo_sweep_many_bc(int32_t L, uint32_t mask, int periodic, uint64_t seed, uint64_t sample0,
+                      int64_t count, int nthreads, int32_t *nstar, int32_t *mass, double times[3]);
 
 /* Cluster labels of the first n sites of the order (label = smallest site index
  * of the cluster; -1 for empty sites), by union-find.  labels has N entries. */

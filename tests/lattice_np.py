@@ -66,3 +66,75 @@ def spans(L, labels):
     lo = set(labels[occ[x0 == 0]].tolist())
     hi = set(labels[occ[x0 == L - 1]].tolist())
     return bool(lo & hi)
+
+
+def wrapping_roots(L, mask, occupied_sites):
+    """Labels (as in components) of the clusters that wrap around axis 0 on the
+    periodic lattice (L >= 5), and the cluster sizes, by breadth-first search:
+    each cluster gets unwrapped x0 coordinates along a BFS tree, and it wraps iff
+    some edge t = s + d of it has u(t) != u(s) + d0 (the loop that edge closes
+    winds around axis 0).  Independent of any union-find."""
+    from collections import deque
+
+    assert L >= 5
+    N = L**5
+    occ = np.zeros(N, dtype=bool)
+    occ[np.asarray(occupied_sites, dtype=np.int64)] = True
+    offs = shell_offsets(mask)
+    strides = L ** np.arange(5)
+
+    def nbrs(s):
+        y = np.mod(coords(L, [s])[0] + offs, L)
+        t = (y * strides).sum(axis=1)
+        keep = occ[t]
+        return t[keep], offs[keep, 0]
+
+    u = {}
+    size = {}
+    wraps = set()
+    for start in np.nonzero(occ)[0]:
+        start = int(start)
+        if start in u:
+            continue
+        u[start] = 0
+        q = deque([start])
+        members = 0
+        bad = False
+        while q:
+            s = q.popleft()
+            members += 1
+            ts, d0s = nbrs(s)
+            for t, d0 in zip(ts.tolist(), d0s.tolist()):
+                if t not in u:
+                    u[t] = u[s] + d0
+                    q.append(t)
+                elif u[t] != u[s] + d0:
+                    bad = True
+        size[start] = members
+        if bad:
+            wraps.add(start)
+    return wraps, size
+
+
+def first_wrap(L, mask, order):
+    """(n*, mass) of the first cluster wrapping around axis 0 along the order
+    (0, 0 if none within it), by bisection on n (wrapping is monotone: a
+    cluster only grows and a loop once formed stays)."""
+    order = np.asarray(order)
+
+    def wrapped(n):
+        w, _ = wrapping_roots(L, mask, order[:n])
+        return bool(w)
+
+    if len(order) == 0 or not wrapped(len(order)):
+        return 0, 0
+    lo, hi = 0, len(order)      # wrapped(lo) false, wrapped(hi) true
+    while hi - lo > 1:
+        mid = (lo + hi) // 2
+        if wrapped(mid):
+            hi = mid
+        else:
+            lo = mid
+    w, size = wrapping_roots(L, mask, order[:hi])
+    assert len(w) == 1
+    return hi, size[next(iter(w))]
