@@ -6,9 +6,11 @@
  * The method (Malarz & Woloszyn, "Random site percolation with complex
  * neighborhoods in five dimension"):
  *   - Sec. I: sites of an L^5 lattice are occupied at random; a cluster that
- *     connects opposite borders "spans"; here the borders are the faces
- *     x0 = 0 and x0 = L-1 and boundaries are free (no wrapping) for every
- *     first-spanning call; the largest-cluster call also takes periodic ones;
+ *     connects opposite borders "spans"; under free boundaries the borders are
+ *     the faces x0 = 0 and x0 = L-1; under periodic boundaries (every
+ *     coordinate mod L) a cluster "spans" when it wraps around axis 0, i.e.
+ *     holds a loop whose unwrapped x0 displacement is a non-zero multiple of
+ *     L (Newman & Ziff 2001, Sec. III);
  *   - Sec. II.A.2, eqs. (7)-(8), Table I: a neighbourhood is any non-empty set
  *     of coordination zones 1..7, zone k being the shell r^2 = k (10, 40, 80,
  *     90, 112, 240, 320 sites); bit k-1 of zone_mask selects zone k;
@@ -49,9 +51,9 @@ extern "C" {
 #define NZ_EWORKSPACE (-5)    /* the caller's workspace is too small */
 
 #define NZ_FREE 0             /* free boundaries */
-#define NZ_PERIODIC 1         /* periodic boundaries (coordinates mod L, L >= 5): no borders, so no
-                                 spanning test; accepted by nz_smax_window only (the first-spanning
-                                 entry points return NZ_EUNSUPPORTED) */
+#define NZ_PERIODIC 1         /* periodic boundaries (coordinates mod L, L >= 5): n* and mass refer
+                                 to the first cluster that wraps around axis 0; L < 5 gives
+                                 NZ_EUNSUPPORTED (two offsets could then reach one site) */
 
 /* Message describing the last failure on the calling thread (never NULL). */
 const char *nz_last_error(void);
@@ -67,7 +69,7 @@ int nz_coordination(uint32_t zone_mask);
 /*
  * nz_sweep -- n* and spanning mass of samples 0 .. nsamples-1 (Sec. II.B).
  *   L          lattice side, 1 <= L <= 55 (N = L^5 < 2^29);
- *   zone_mask  1..127;  boundary  NZ_FREE (NZ_PERIODIC: NZ_EUNSUPPORTED);
+ *   zone_mask  1..127;  boundary  NZ_FREE or NZ_PERIODIC (L >= 5);
  *   seed  any 64-bit value;
  *   nstar      HOST array of nsamples int32, written;
  *   mass       HOST array of nsamples int32, written; may be NULL.
@@ -193,6 +195,10 @@ int nz_batch_workspace_bytes(const nz_job *jobs, int32_t njobs, const nz_tuning 
  *   tune           may be NULL;  stream  hipStream_t (NULL: default stream).
  * Returns after the results are in d_nstar / d_mass (the call synchronises the
  * stream, because samples whose key band or bucket ran short are redone).
+ * Jobs with NZ_PERIODIC run in chunks of their own, one site per step with
+ * their state in HBM whatever the tuning says: each site keeps its x0
+ * displacement from its parent beside the parent (8 bytes a site instead of
+ * 4), and their bulk prefill backs off when its state already wraps.
  */
 int nz_sweep_batch(const nz_job *jobs, int32_t njobs, void *d_ws, size_t ws_bytes,
                    int32_t *d_nstar, int32_t *d_mass, int32_t *h_backoffs,

@@ -187,6 +187,7 @@ struct Plan {
     int32_t prefix_mul;  // prefill list capacity multiplier
     double prio;
     int64_t win_lo, win_hi;   // smax mode: S_max(n) for n in [win_lo, win_hi) (win_hi = 0: off)
+    bool wrap;           // periodic first-wrap sample (64-bit union-find entries)
 };
 
 uint64_t rank_to_key(int64_t n, int64_t N)
@@ -251,7 +252,7 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
     } else {
         s.prefix_cap = 0;
     }
-    s.par = align_up(static_cast<size_t>(N) * 4);
+    s.par = align_up(static_cast<size_t>(N) * (p.wrap ? 8 : 4));
     s.occ = align_up(static_cast<size_t>((N + 63) / 64) * 8);
     s.keys = align_up(static_cast<size_t>(nb_alloc) * s.cap * 8);
     s.sites = align_up(static_cast<size_t>(nb_alloc) * s.cap * 4);
@@ -417,6 +418,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             p.prio = J.prio > 0 ? J.prio : static_cast<double>(std::max<int64_t>(1, p.band_hi - p.n0)) * (1.0 + z / 64.0);
             p.win_lo = smax ? smax->win_lo : 0;
             p.win_hi = smax ? smax->win_hi : 0;
+            p.wrap = J.boundary == NZ_PERIODIC && !smax;
             todo.push_back(p);
         }
     }
@@ -426,7 +428,11 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
     int rounds = 0;
     while (!todo.empty()) {
         if (++rounds > 64) return fail(NZ_EDEVICE, "samples still unfinished after 64 redo rounds");
-        std::stable_sort(todo.begin(), todo.end(), [](const Plan &a, const Plan &b) { return a.prio > b.prio; });
+        // free-boundary samples first, then the periodic first-wrap ones: a chunk
+        // holds one kind only, since the two use different kernels
+        std::stable_sort(todo.begin(), todo.end(), [](const Plan &a, const Plan &b) {
+            return a.wrap != b.wrap ? b.wrap : a.prio > b.prio;
+        });
         std::vector<Plan> redo;
         size_t pos = 0;
         while (pos < todo.size()) {
@@ -438,6 +444,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             std::vector<Sizes> sizes;
             size_t used = head;
             while (pos < todo.size() && static_cast<int32_t>(chunk.size()) < cmax) {
+                if (!chunk.empty() && todo[pos].wrap != chunk.front().wrap) break;
                 Sizes s = plan_sizes(todo[pos], tune.bucket_log2);
                 if (used + s.total > ws_bytes) break;
                 used += s.total;
@@ -451,6 +458,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             }
             ++g_stats[0];
             const int32_t n = static_cast<int32_t>(chunk.size());
+            const bool wrap_chunk = chunk.front().wrap;
 
             // ---- descriptors, grouped by L for the keys launches
             std::vector<int32_t> byL(n);
@@ -494,6 +502,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 d.win_lo = static_cast<int32_t>(p.win_lo);
                 d.win_hi = static_cast<int32_t>(p.win_hi);
                 d.periodic = J.boundary == NZ_PERIODIC ? 1 : 0;
+                d.wrap = p.wrap ? 1 : 0;
                 out_index[di] = p.out;
                 chunk_of_desc[di] = ci;
                 desc_of_chunk[ci] = di;
@@ -553,7 +562,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 const int32_t bx_hook = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(256, (max_site + 1023) / 1024)));
                 const int32_t bx_site = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(1024, (max_site + 1023) / 1024)));
                 HIP_TRY(nz::launch_prefill(d_desc, d_list, static_cast<int32_t>(prefill_list.size()), bx_hook, bx_site, d_tabs, ws,
-                                           d_state, smax != nullptr, st));
+                                           d_state, smax != nullptr, wrap_chunk, st));
                 // Resolve backoffs inside the chunk: samples whose bulk state already
                 // spans are re-keyed and re-labelled from n0 - b, and if that spans
                 // too from n0 - 3b, so they join this chunk's sweep instead of a
@@ -590,46 +599,63 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                         HIP_TRY(nz::launch_keys(d_desc, d_list, a, b - a, desc[again[a]].N, ws, d_state, st));
                         a = b;
                     }
-                    HIP_TRY(nz::launch_prefill(d_desc, d_list, na, bx_hook, bx_site, d_tabs, ws, d_state, smax != nullptr, st));
+                    HIP_TRY(nz::launch_prefill(d_desc, d_list, na, bx_hook, bx_site, d_tabs, ws, d_state, smax != nullptr,
+                                               wrap_chunk, st));
                 }
             }
             if (pe) HIP_TRY(hipEventRecord(pe->ev[2], st));
             HIP_TRY(nz::launch_sort(d_desc, n, max_nb, max_cap, ws, st));
             if (pe) HIP_TRY(hipEventRecord(pe->ev[3], st));
 
-            int residency = tune.residency == 3 ? 2 : (tune.residency == 1 ? 1 : 0);
-            const uint32_t occ_words = ((max_N + 63) / 64) * 2;
-            uint32_t lds_words = residency == 2 ? occ_words + max_N : (residency == 1 ? occ_words : 0);
-            // sweep mode: 2 = 64 sites per step for every sample; auto = 64 sites per
-            // step for z <= 512 (wider neighbourhoods are faster one site at a time)
-            int32_t min_z = 1 << 30;
-            for (const NzSample &d : desc) min_z = std::min(min_z, d.z);
-            const int32_t blk_zmax = tune.sweep_mode == 2 ? 892 : 512;
-            const bool block = tune.sweep_mode == 2 || (tune.sweep_mode == 0 && min_z <= blk_zmax);
-            if (block) lds_words += nz::block_lds_words();
-            int wg_waves = tune.wg_waves ? tune.wg_waves : (residency ? 1 : 4);
-            int wps = tune.waves_per_simd ? tune.waves_per_simd : 8;
-            size_t lds_wg = static_cast<size_t>(lds_words) * 4 * wg_waves;
-            if (lds_wg > dev.lds_per_block)
-                return fail(NZ_EUNSUPPORTED, "residency %d needs %zu bytes of LDS per workgroup; the device allows %zu",
-                            tune.residency, lds_wg, dev.lds_per_block);
-            int wgs_per_cu = std::max(1, 4 * wps / wg_waves);
-            if (lds_wg > 0) wgs_per_cu = std::max<int>(1, std::min<size_t>(wgs_per_cu, dev.lds_per_cu / lds_wg));
-            int grid = dev.cus * wgs_per_cu;
-            grid = std::min(grid, (n + wg_waves - 1) / wg_waves);
-            NzSweepArgs args;
-            args.desc = d_desc;
-            args.queue = d_queue;
-            args.nqueue = n;
-            args.qhead = d_qhead;
-            args.tabs = d_tabs;
-            args.ws = ws;
-            args.state = d_state;
-            args.lds_words = lds_words;
-            args.dcap = tune.dcap;
-            args.blk_old = env_blk_old();
-            args.blk_zmax = blk_zmax;
-            HIP_TRY(nz::launch_sweep(nch_for(max_z), residency, block, args, d_nstar, d_mass, d_outidx, grid, wg_waves, st));
+            if (wrap_chunk) {
+                // periodic first-wrap: one site per step, state in HBM, 4 waves
+                // per workgroup
+                NzSweepArgs args{};
+                args.desc = d_desc;
+                args.queue = d_queue;
+                args.nqueue = n;
+                args.qhead = d_qhead;
+                args.tabs = d_tabs;
+                args.ws = ws;
+                args.state = d_state;
+                args.dcap = tune.dcap;
+                const int grid = std::max(1, std::min(dev.cus * 8, (n + 3) / 4));
+                HIP_TRY(nz::launch_wrap_sweep(nch_for(max_z), args, d_nstar, d_mass, d_outidx, grid, st));
+            } else {
+                int residency = tune.residency == 3 ? 2 : (tune.residency == 1 ? 1 : 0);
+                const uint32_t occ_words = ((max_N + 63) / 64) * 2;
+                uint32_t lds_words = residency == 2 ? occ_words + max_N : (residency == 1 ? occ_words : 0);
+                // sweep mode: 2 = 64 sites per step for every sample; auto = 64 sites per
+                // step for z <= 512 (wider neighbourhoods are faster one site at a time)
+                int32_t min_z = 1 << 30;
+                for (const NzSample &d : desc) min_z = std::min(min_z, d.z);
+                const int32_t blk_zmax = tune.sweep_mode == 2 ? 892 : 512;
+                const bool block = tune.sweep_mode == 2 || (tune.sweep_mode == 0 && min_z <= blk_zmax);
+                if (block) lds_words += nz::block_lds_words();
+                int wg_waves = tune.wg_waves ? tune.wg_waves : (residency ? 1 : 4);
+                int wps = tune.waves_per_simd ? tune.waves_per_simd : 8;
+                size_t lds_wg = static_cast<size_t>(lds_words) * 4 * wg_waves;
+                if (lds_wg > dev.lds_per_block)
+                    return fail(NZ_EUNSUPPORTED, "residency %d needs %zu bytes of LDS per workgroup; the device allows %zu",
+                                tune.residency, lds_wg, dev.lds_per_block);
+                int wgs_per_cu = std::max(1, 4 * wps / wg_waves);
+                if (lds_wg > 0) wgs_per_cu = std::max<int>(1, std::min<size_t>(wgs_per_cu, dev.lds_per_cu / lds_wg));
+                int grid = dev.cus * wgs_per_cu;
+                grid = std::min(grid, (n + wg_waves - 1) / wg_waves);
+                NzSweepArgs args;
+                args.desc = d_desc;
+                args.queue = d_queue;
+                args.nqueue = n;
+                args.qhead = d_qhead;
+                args.tabs = d_tabs;
+                args.ws = ws;
+                args.state = d_state;
+                args.lds_words = lds_words;
+                args.dcap = tune.dcap;
+                args.blk_old = env_blk_old();
+                args.blk_zmax = blk_zmax;
+                HIP_TRY(nz::launch_sweep(nch_for(max_z), residency, block, args, d_nstar, d_mass, d_outidx, grid, wg_waves, st));
+            }
             if (smax)
                 HIP_TRY(nz::launch_winsum(d_desc, d_state, n, static_cast<int32_t>(smax->win_hi - smax->win_lo), ws,
                                           smax->d_out, st));
@@ -712,14 +738,17 @@ size_t batch_bytes(const nz_job *jobs, int32_t njobs, const Tune &tune)
     std::vector<size_t> per;
     TablePool pool;
     int32_t maxL = 1;
+    bool any_wrap = false;
     for (int j = 0; j < njobs; ++j) {
         int32_t z;
         pool.get(jobs[j].zone_mask, jobs[j].L, &z);
+        any_wrap = any_wrap || jobs[j].boundary == NZ_PERIODIC;
         Plan p{};
         p.L = jobs[j].L;
         p.mask = jobs[j].zone_mask;
         p.n0 = jobs[j].n0 > 0 ? jobs[j].n0 : 0;
         p.backoff = jobs[j].backoff;   // sizes the band of a first backoff too
+        p.wrap = jobs[j].boundary == NZ_PERIODIC;
         const int64_t N = pow5(p.L);
         p.band_hi = jobs[j].band_hi > 0 ? std::min<int64_t>(jobs[j].band_hi, N) : default_band_hi(p.L, p.mask, p.n0);
         if (p.band_hi <= p.n0) p.band_hi = std::min<int64_t>(N, p.n0 + 4096);
@@ -737,6 +766,7 @@ size_t batch_bytes(const nz_job *jobs, int32_t njobs, const Tune &tune)
     full.mask = 127;
     full.band_hi = pow5(maxL);
     full.prefix_mul = 1;
+    full.wrap = any_wrap;
     total += plan_sizes(full, tune.bucket_log2).total;
     return total;
 }
@@ -806,10 +836,6 @@ NZ_API int nz_sweep_batch(const nz_job *jobs, int32_t njobs, void *d_ws, size_t 
         total += jobs[j].nsamples;
     }
     if (total == 0) return NZ_OK;
-    for (int j = 0; j < njobs; ++j)
-        if (jobs[j].boundary == NZ_PERIODIC)
-            return fail(NZ_EUNSUPPORTED, "job %d: first spanning on a periodic lattice (wrapping) is not implemented; "
-                                         "periodic boundaries serve nz_smax_window", j);
     if (!d_ws || !d_nstar) return fail(NZ_EINVAL, "workspace or n* output is NULL");
     if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(NZ_EINVAL, "workspace must be 256-byte aligned");
     Tune t;
@@ -851,9 +877,6 @@ NZ_API int nz_sweep(int32_t L, uint32_t zone_mask, int32_t boundary, int64_t nsa
     j.nsamples = nsamples;
     j.n0 = -1;
     if (int rc = check_job(j, 0)) return rc;
-    if (boundary == NZ_PERIODIC)
-        return fail(NZ_EUNSUPPORTED, "first spanning on a periodic lattice (wrapping) is not implemented; "
-                                     "periodic boundaries serve nz_smax_window");
     if (nsamples == 0) return NZ_OK;
     if (!nstar) return fail(NZ_EINVAL, "nstar is NULL");
     if (nsamples > 0x7FFFFFFF) return fail(NZ_EINVAL, "nsamples too large");

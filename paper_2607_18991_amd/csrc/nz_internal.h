@@ -60,7 +60,9 @@ struct NzSample {
     int32_t win_lo;
     int32_t win_hi;
     int32_t periodic;     // 1: coordinates wrap mod L (L >= 5); no borders, so no border flags
-    int32_t pad;
+    int32_t wrap;         // 1: periodic first-wrap sweep; entries of off_par are 64-bit
+                          //    (low half the parent word, high half the x0 displacement
+                          //    from the parent)
 };
 
 // Per-sample result/state record written by the kernels.

@@ -271,12 +271,14 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
         // prefilled: parent = itself, staged even sites first, then odd
         const uint32_t ne = static_cast<uint32_t>(__popcll(be));
         if (pre0) {
-            c.par[i0] = static_cast<int32_t>(i0);
+            if (d.wrap) reinterpret_cast<uint64_t *>(c.par)[i0] = i0;   // itself, displacement 0
+            else c.par[i0] = static_cast<int32_t>(i0);
             slice[nstaged + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(be >> 32),
                                                       __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(be), 0u))] = i0;
         }
         if (pre1) {
-            c.par[i1] = static_cast<int32_t>(i1);
+            if (d.wrap) reinterpret_cast<uint64_t *>(c.par)[i1] = i1;
+            else c.par[i1] = static_cast<int32_t>(i1);
             slice[nstaged + ne + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(bo >> 32),
                                                            __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bo), 0u))] = i1;
         }
@@ -450,7 +452,7 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
     const int sid = list[y];
     const NzSample &d = desc[sid];
     const int32_t n0 = state[sid].n0;
-    if (n0 > d.prefix_cap) return;
+    if (n0 > d.prefix_cap || d.wrap) return;
     const int32_t L = d.L;
     const int32_t zh = d.z >> 1;
     const uint64_t magic = d.magic;
@@ -523,7 +525,7 @@ __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__rest
     const int sid = list[y];
     const NzSample &d = desc[sid];
     const int32_t n0 = state[sid].n0;
-    if (n0 > d.prefix_cap) return;
+    if (n0 > d.prefix_cap || d.wrap) return;
     const uint32_t L = static_cast<uint32_t>(d.L);
     int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
@@ -557,6 +559,7 @@ __global__ __launch_bounds__(256) void nz_accum_kernel(const NzSample *__restric
     if (!xcd_slot(nlist, bx, y, x)) return;
     const int sid = list[y];
     const NzSample &d = desc[sid];
+    if (d.wrap) return;
     const int32_t n0 = state[sid].n0;
     if (n0 > d.prefix_cap) {
         if (x == 0 && threadIdx.x == 0) state[sid].status = NZ_ST_PREFIX;
@@ -1330,6 +1333,390 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
     }
 }
 
+// ---------------------------------------------------------------------------
+// Periodic boundaries: n* is the first addition after which a cluster wraps
+// around axis 0 (Newman & Ziff 2001, Sec. III).
+//
+// Every site's entry is one 64-bit word: the low half is the parent word of the
+// free-boundary sweep (a parent index, or a root word), the high half the x0
+// displacement of the site from its parent in the unwrapped lattice (0 at a
+// root).  A site's displacement from its root is the sum along its path.  Every
+// write stores an (ancestor, displacement to it) pair in one 64-bit store, so
+// any entry a lane or thread reads, however stale, is consistent.  An edge
+// t = s + d inside one cluster closes a loop, and the loop winds around axis 0
+// exactly when the displacements of s and t from their common root differ by
+// anything but d0; the cluster then wraps and takes both border flags, the
+// state the spanning test looks for.
+
+__device__ __forceinline__ uint64_t wword(uint32_t par, int32_t dx)
+{
+    return (static_cast<uint64_t>(static_cast<uint32_t>(dx)) << 32) | par;
+}
+__device__ __forceinline__ int32_t wpar(uint64_t e) { return static_cast<int32_t>(static_cast<uint32_t>(e)); }
+__device__ __forceinline__ int32_t wdx(uint64_t e) { return static_cast<int32_t>(e >> 32); }
+
+// x0 component of an offset: the axis-0 field of its code has bit d0 + 2 set.
+__device__ __forceinline__ int32_t code_d0(uint32_t code) { return __builtin_ctz(code | 32u) - 2; }
+
+// Prefill phase: a root points to itself with displacement 0.  Root of x and
+// the displacement of x from it; path splitting (each entry on the way skips to
+// its grandparent, displacements added).
+__device__ __forceinline__ int32_t ccw_find(uint64_t *pw, int32_t x, int32_t &disp)
+{
+    uint64_t e = ld_w(&pw[x]);
+    int32_t D = 0;
+    while (wpar(e) != x) {
+        const int32_t p = wpar(e);
+        const uint64_t g = ld_w(&pw[p]);
+        if (wpar(g) != p) st_w(&pw[x], wword(static_cast<uint32_t>(wpar(g)), wdx(e) + wdx(g)));
+        D += wdx(e);
+        x = p;
+        e = g;
+    }
+    disp = D;
+    return x;
+}
+
+// Hook with displacements: as the free-boundary hook (CAS links the larger root
+// below the smaller), the hooked root taking its displacement from the smaller
+// one through the edge.  An edge whose ends already share a root is checked
+// instead; a winding loop means the prefilled state already wraps, and the
+// sample backs off.
+__global__ __launch_bounds__(256) void nz_hookw_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
+                                                       int32_t nlist, int32_t bx, const NzOffset *__restrict__ tabs,
+                                                       uint8_t *__restrict__ ws, NzState *__restrict__ state)
+{
+    int32_t y, x;
+    if (!xcd_slot(nlist, bx, y, x)) return;
+    const int sid = list[y];
+    const NzSample &d = desc[sid];
+    const int32_t n0 = state[sid].n0;
+    if (n0 > d.prefix_cap || !d.wrap) return;
+    const int32_t L = d.L;
+    const int32_t zh = d.z >> 1;
+    const uint64_t magic = d.magic;
+    uint64_t *pw = reinterpret_cast<uint64_t *>(ws + d.off_par);
+    const uint32_t *occ = reinterpret_cast<const uint32_t *>(ws + d.off_occ);
+    const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
+    const NzOffset *tab = tabs + d.tab;
+    bool wraps = false;
+    for (int32_t i = x * 256 + static_cast<int32_t>(threadIdx.x); i < n0; i += bx * 256) {
+        const int32_t s = static_cast<int32_t>(prefix[i]);
+        const uint32_t pc = pack_coords(static_cast<uint32_t>(s), static_cast<uint32_t>(L), magic);
+        const uint32_t A = allowed_axis(pc & 63, L) | (allowed_axis((pc >> 6) & 63, L) << 5) |
+                           (allowed_axis((pc >> 12) & 63, L) << 10) | (allowed_axis((pc >> 18) & 63, L) << 15) |
+                           (allowed_axis(pc >> 24, L) << 20);
+        int32_t u = -1, Du = 0;   // a root (or ancestor) of s and the displacement of s from it
+        for (int32_t k0 = 0; k0 < zh; k0 += HOOK_UNROLL) {
+            int32_t t[HOOK_UNROLL], d0[HOOK_UNROLL];
+            uint32_t w[HOOK_UNROLL];
+#pragma unroll
+            for (int q = 0; q < HOOK_UNROLL; ++q) {
+                NzOffset o;
+                o.stride = 0;
+                o.code = 0xFFFFFFFFu;
+                if (k0 + q < zh) o = tab[k0 + q];
+                const uint32_t out = o.code & ~A;
+                const bool ok = (o.code & ~kCodeBits) == 0u;   // every real offset, wrapped
+                t[q] = s + o.stride + (out ? wrap_fix(out, L) : 0);
+                d0[q] = code_d0(o.code);
+                w[q] = ok ? occ[static_cast<uint32_t>(t[q]) >> 5] : 0u;
+            }
+#pragma unroll
+            for (int q = 0; q < HOOK_UNROLL; ++q) {
+                if (!((w[q] >> (t[q] & 31)) & 1u)) continue;
+                if (u < 0) u = ccw_find(pw, s, Du);
+                int32_t Dv;
+                int32_t v = ccw_find(pw, t[q], Dv);
+                for (;;) {
+                    if (u == v) {
+                        if (Du + d0[q] != Dv) wraps = true;
+                        break;
+                    }
+                    const int32_t hi = max(u, v), lo = min(u, v);
+                    // x0(u) = x0(s) - Du and x0(v) = x0(s) + d0 - Dv
+                    const int32_t dx = hi == u ? Dv - Du - d0[q] : Du + d0[q] - Dv;
+                    uint64_t expected = wword(static_cast<uint32_t>(hi), 0);
+                    if (__hip_atomic_compare_exchange_strong(&pw[hi], &expected, wword(static_cast<uint32_t>(lo), dx),
+                                                             __ATOMIC_RELAXED, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                        if (hi == u) {
+                            u = lo;
+                            Du += dx;
+                        }
+                        break;
+                    }
+                    // hi is no longer a root: go on from the entry the CAS returned
+                    int32_t Dp;
+                    if (u == hi) {
+                        u = ccw_find(pw, wpar(expected), Dp);
+                        Du += wdx(expected) + Dp;
+                    } else {
+                        u = ccw_find(pw, u, Dp);
+                        Du += Dp;
+                    }
+                    if (v == hi) {
+                        v = ccw_find(pw, wpar(expected), Dp);
+                        Dv += wdx(expected) + Dp;
+                    } else {
+                        v = ccw_find(pw, v, Dp);
+                        Dv += Dp;
+                    }
+                }
+            }
+        }
+    }
+    if (wraps) state[sid].status = NZ_ST_BACKOFF;
+}
+
+// Compress with displacements: every member holds (root, displacement from the
+// root), every root its root word (size 1, no border flags).  Walks are
+// read-only and each thread writes only its own entry, as in the
+// free-boundary compress.
+__global__ __launch_bounds__(256) void nz_compressw_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
+                                                           int32_t nlist, int32_t bx, uint8_t *__restrict__ ws,
+                                                           NzState *__restrict__ state)
+{
+    int32_t y, x;
+    if (!xcd_slot(nlist, bx, y, x)) return;
+    const int sid = list[y];
+    const NzSample &d = desc[sid];
+    const int32_t n0 = state[sid].n0;
+    if (n0 > d.prefix_cap || !d.wrap) return;
+    uint64_t *pw = reinterpret_cast<uint64_t *>(ws + d.off_par);
+    const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
+    for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
+        const int32_t s = static_cast<int32_t>(prefix[k]);
+        int32_t r = s, D = 0;
+        uint64_t e = ld_w(&pw[r]);
+        while (wpar(e) >= 0 && wpar(e) != r) {
+            D += wdx(e);
+            r = wpar(e);
+            e = ld_w(&pw[r]);
+        }
+        st_w(&pw[s], r == s ? wword(NZ_ROOT | 1u, 0) : wword(static_cast<uint32_t>(r), D));
+    }
+}
+
+// Sizes of the prefilled clusters: members add themselves to the low half of
+// their root's entry.
+__global__ __launch_bounds__(256) void nz_accumw_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
+                                                        int32_t nlist, int32_t bx, uint8_t *__restrict__ ws,
+                                                        NzState *__restrict__ state)
+{
+    int32_t y, x;
+    if (!xcd_slot(nlist, bx, y, x)) return;
+    const int sid = list[y];
+    const NzSample &d = desc[sid];
+    if (!d.wrap) return;
+    const int32_t n0 = state[sid].n0;
+    if (n0 > d.prefix_cap) {
+        if (x == 0 && threadIdx.x == 0) state[sid].status = NZ_ST_PREFIX;
+        return;
+    }
+    uint64_t *pw = reinterpret_cast<uint64_t *>(ws + d.off_par);
+    const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
+    for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
+        const int32_t s = static_cast<int32_t>(prefix[k]);
+        const int32_t r = wpar(pw[s]);
+        if (r >= 0) atomicAdd(reinterpret_cast<uint32_t *>(&pw[r]), 1u);   // low half: the root word
+    }
+}
+
+// Sweep phase: root of x, its root word and the displacement of x from it; path
+// halving with displacements added.
+__device__ __forceinline__ void wrap_find(uint64_t *pw, int32_t x, int32_t &root, uint32_t &word, int32_t &disp)
+{
+    uint64_t e = ld_w(&pw[x]);
+    int32_t D = 0;
+    while (wpar(e) >= 0) {
+        const int32_t p = wpar(e);
+        const uint64_t g = ld_w(&pw[p]);
+        if (wpar(g) < 0) {
+            D += wdx(e);
+            x = p;
+            e = g;
+            break;
+        }
+        const uint64_t h = wword(static_cast<uint32_t>(wpar(g)), wdx(e) + wdx(g));
+        st_w(&pw[x], h);
+        D += wdx(h);
+        x = wpar(g);
+        e = ld_w(&pw[x]);
+    }
+    root = x;
+    word = static_cast<uint32_t>(wpar(e));
+    disp = D;
+}
+
+// Merge the D distinct roots held by lanes 0..D-1 into the largest (ties: the
+// smaller index).  lq is x0(new site) - x0(lane's root); each attached root
+// takes its displacement from the survivor.  Returns the survivor and, through
+// the references, the total size, the flags and the survivor's lq.
+__device__ __forceinline__ int32_t wrap_merge(uint64_t *pw, int D, int32_t lroot, uint32_t lword, int32_t lq,
+                                              uint32_t wrapfl, uint32_t &total, uint32_t &flags, int32_t &qbest)
+{
+    const uint32_t lane = lane_id();
+    int32_t best = bcast(lroot, 0);
+    uint32_t bestsz = bcast(lword, 0) & NZ_SIZE;
+    int bl = 0;
+    total = 0;
+    flags = wrapfl;
+    for (int l = 0; l < D; ++l) {
+        const int32_t r = bcast(lroot, l);
+        const uint32_t w = bcast(lword, l);
+        const uint32_t sz = w & NZ_SIZE;
+        total += sz;
+        flags |= w & NZ_FLAGS;
+        if (sz > bestsz || (sz == bestsz && r < best)) {
+            best = r;
+            bestsz = sz;
+            bl = l;
+        }
+    }
+    qbest = bcast(lq, bl);
+    // x0(root) - x0(best) = (x0(site) - lq) - (x0(site) - qbest)
+    if (static_cast<int>(lane) < D && lroot != best) st_w(&pw[lroot], wword(static_cast<uint32_t>(best), qbest - lq));
+    st_w(&pw[best], wword(NZ_ROOT | flags | total, 0));   // every lane, same value
+    return best;
+}
+
+// One addition under periodic boundaries: as the free-boundary step, with the
+// new site's displacement from each neighbouring root carried along and
+// compared whenever two neighbours share a root.
+template <int NCH>
+__device__ __forceinline__ void wrap_step(uint32_t *occ, uint64_t *pw, const SiteStep<NCH> &cur, const int32_t (&od0)[NCH],
+                                          int dcap, uint32_t &total, uint32_t &flags)
+{
+    const uint32_t lane = lane_id();
+    const int32_t s = cur.s;
+    st_w(&occ[static_cast<uint32_t>(s) >> 5], cur.own | (1u << (s & 31)));
+
+    int32_t lroot = s, lq = 0;
+    uint32_t lword = NZ_ROOT | 1u;
+    uint32_t wrapfl = 0;
+    int D = 1;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const bool o = cur.inb[c] && ((cur.word[c] >> (cur.tn[c] & 31)) & 1u);
+        uint64_t mk = __ballot(o);
+        if (!mk) continue;
+        int32_t root = 0, disp = 0;
+        uint32_t rw = 0;
+        if (o) wrap_find(pw, cur.tn[c], root, rw, disp);
+        // t = s + d: x0(s) - x0(root) = disp - d0
+        const int32_t q = disp - od0[c];
+        bool stale = false;   // a flush since these finds may have linked their roots
+        while (mk) {
+            const int l = __builtin_ctzll(mk);
+            mk &= mk - 1;
+            int32_t rr = bcast(root, l);
+            uint32_t rrw = bcast(rw, l);
+            int32_t qq = bcast(q, l);
+            if (stale) {
+                int32_t extra;
+                wrap_find(pw, rr, rr, rrw, extra);
+                qq += extra;
+            }
+            const uint64_t hit = __ballot(static_cast<int>(lane) < D && lroot == rr);
+            if (hit) {
+                if (bcast(lq, __builtin_ctzll(hit)) != qq) wrapfl = NZ_FLAGS;
+                continue;
+            }
+            if (D == dcap) {
+                uint32_t tot, flg;
+                int32_t qb;
+                const int32_t w = wrap_merge(pw, D, lroot, lword, lq, wrapfl, tot, flg, qb);
+                lroot = lane == 0 ? w : lroot;
+                lword = lane == 0 ? (NZ_ROOT | flg | tot) : lword;
+                lq = lane == 0 ? qb : lq;
+                D = 1;
+                stale = true;
+            }
+            lroot = static_cast<int>(lane) == D ? rr : lroot;
+            lword = static_cast<int>(lane) == D ? rrw : lword;
+            lq = static_cast<int>(lane) == D ? qq : lq;
+            ++D;
+        }
+    }
+    int32_t qb;
+    wrap_merge(pw, D, lroot, lword, lq, wrapfl, total, flags, qb);
+}
+
+// Persistent first-wrap sweep: one wave per sample, one site per step, state
+// in HBM (the entries are twice as wide as in the free-boundary sweep).
+template <int NCH>
+__global__ __launch_bounds__(256) void nz_wrap_sweep_kernel(NzSweepArgs a, SweepOut out)
+{
+    __shared__ int32_t claim[4];
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x >> 6;
+    for (;;) {
+        if (lane == 0) claim[wave] = atomicAdd(a.qhead, 1);
+        __builtin_amdgcn_wave_barrier();
+        const int qi = __builtin_amdgcn_readfirstlane(ld_w(&claim[wave]));
+        __builtin_amdgcn_wave_barrier();
+        if (qi >= a.nqueue) break;
+        const int sid = a.queue[qi];
+        if (a.state[sid].status != NZ_ST_PENDING) continue;
+        const NzSample &d = a.desc[sid];
+        const int32_t L = d.L;
+        const int32_t z = d.z;
+        SweepMem<RES_HBM> m;
+        m.occ_g = reinterpret_cast<uint32_t *>(a.ws + d.off_occ);
+        m.par_g = nullptr;   // the occupancy side only; entries go through pw
+        m.lbase = 0;
+        m.occ_words = 0;
+        uint64_t *pw = reinterpret_cast<uint64_t *>(a.ws + d.off_par);
+        const NzOffset *tab = a.tabs + d.tab;
+        int32_t ostride[NCH], od0[NCH];
+        uint32_t ocode[NCH];
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int32_t j = c * 64 + static_cast<int32_t>(lane);
+            const NzOffset o = j < z ? tab[j] : NzOffset{0, 0xFFFFFFFFu};
+            ostride[c] = o.stride;
+            ocode[c] = o.code;
+            od0[c] = code_d0(o.code);
+        }
+        int32_t r = a.state[sid].n0;
+        int32_t status = NZ_ST_BAND;
+        int32_t nstar = 0, mass = 0;
+        BandCursor bc;
+        bc.init(reinterpret_cast<const uint32_t *>(a.ws + d.off_counts),
+                reinterpret_cast<const uint32_t *>(a.ws + d.off_sites), static_cast<uint32_t>(d.cap), d.nb);
+        SiteStep<NCH> cur;
+        uint32_t pc = 0;
+        int got = bc.next(pc, lane);
+        while (got == 1) {
+            ++r;
+            cur.prepare(m, nullptr, pc, L, ostride, ocode, true);
+            uint32_t total, flags;
+            wrap_step<NCH>(m.occ_g, pw, cur, od0, a.dcap, total, flags);
+            if (flags == NZ_FLAGS) {
+                status = NZ_ST_DONE;
+                nstar = r;
+                mass = static_cast<int32_t>(total);
+                break;
+            }
+            got = bc.next(pc, lane);
+        }
+        if (got < 0) status = NZ_ST_BUCKET;
+        if (status == NZ_ST_BAND && d.full) {
+            status = NZ_ST_DONE;   // every site occupied and nothing wraps
+            nstar = 0;
+            mass = 0;
+        }
+        a.state[sid].status = status;
+        a.state[sid].nstar = nstar;
+        a.state[sid].mass = mass;
+        if (status == NZ_ST_DONE) {
+            const int32_t o = out.out_index[sid];
+            out.nstar[o] = nstar;
+            if (out.mass) out.mass[o] = mass;
+        }
+    }
+}
+
 }  // namespace nz
 
 // ---------------------------------------------------------------------------
@@ -1375,10 +1762,19 @@ hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int3
 }
 
 hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nlist, int32_t bx_hook, int32_t bx_site,
-                          const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, hipStream_t st)
+                          const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, bool wrap, hipStream_t st)
 {
     if (nlist <= 0) return hipSuccess;
     const uint32_t slots8 = static_cast<uint32_t>((nlist + 7) / 8) * 8u;
+    if (wrap) {
+        hipLaunchKernelGGL(nz_hookw_kernel, dim3(static_cast<uint32_t>(bx_hook) * slots8), dim3(256), 0, st, desc, list,
+                           nlist, bx_hook, tabs, ws, state);
+        hipLaunchKernelGGL(nz_compressw_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
+                           nlist, bx_site, ws, state);
+        hipLaunchKernelGGL(nz_accumw_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
+                           nlist, bx_site, ws, state);
+        return hipGetLastError();
+    }
     hipLaunchKernelGGL(nz_hook_kernel, dim3(static_cast<uint32_t>(bx_hook) * slots8), dim3(256), 0, st, desc, list, nlist,
                        bx_hook, tabs, ws, state);
     hipLaunchKernelGGL(nz_compress_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
@@ -1430,6 +1826,21 @@ static hipError_t launch_sweep_r(int nch, const NzSweepArgs &a, const SweepOut &
 }
 
 uint32_t block_lds_words() { return BLK_LDS_WORDS; }
+
+hipError_t launch_wrap_sweep(int nch, const NzSweepArgs &a, int32_t *nstar, int32_t *mass, const int32_t *out_index,
+                             int grid, hipStream_t st)
+{
+    SweepOut o{nstar, mass, out_index};
+    switch (nch) {
+    case 1: hipLaunchKernelGGL(nz_wrap_sweep_kernel<1>, dim3(grid), dim3(256), 0, st, a, o); break;
+    case 2: hipLaunchKernelGGL(nz_wrap_sweep_kernel<2>, dim3(grid), dim3(256), 0, st, a, o); break;
+    case 4: hipLaunchKernelGGL(nz_wrap_sweep_kernel<4>, dim3(grid), dim3(256), 0, st, a, o); break;
+    case 8: hipLaunchKernelGGL(nz_wrap_sweep_kernel<8>, dim3(grid), dim3(256), 0, st, a, o); break;
+    case 14: hipLaunchKernelGGL(nz_wrap_sweep_kernel<14>, dim3(grid), dim3(256), 0, st, a, o); break;
+    default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
 
 hipError_t launch_sweep(int nch, int residency, bool block, const NzSweepArgs &a, int32_t *nstar, int32_t *mass,
                         const int32_t *out_index, int grid, int wg_waves, hipStream_t st)

@@ -27,7 +27,7 @@ def oracle_batch(jobs):
     ns, ms = [], []
     for j in jobs:
         a, b = oracle.sweep_many(j["L"], j["zone_mask"], j["seed"], j.get("sample0", 0), j["nsamples"],
-                                 nthreads=THREADS)
+                                 nthreads=THREADS, periodic=j.get("boundary", nz.NZ_FREE) == nz.NZ_PERIODIC)
         ns.append(a)
         ms.append(b)
     return np.concatenate(ns), np.concatenate(ms)

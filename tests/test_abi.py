@@ -111,9 +111,9 @@ def test_smax_window_validation():
 
 
 def test_boundary_codes():
-    # periodic boundaries serve the largest-cluster call only, for L >= 5
+    # periodic boundaries need L >= 5; other codes are invalid
     with pytest.raises(nz.NzError) as e:
-        nz.nz_sweep(6, 1, 4, 1, boundary=nz.NZ_PERIODIC)
+        nz.nz_sweep(4, 1, 4, 1, boundary=nz.NZ_PERIODIC)
     assert e.value.code == nz.NZ_EUNSUPPORTED
     with pytest.raises(nz.NzError) as e:
         nz.nz_sweep(6, 1, 4, 1, boundary=2)
