@@ -205,7 +205,7 @@ struct Sizes {
     int64_t n0b[2];
     uint64_t T0b[2];
     int32_t nbb[2];
-    size_t par, occ, keys, sites, counts, prefix, win, total;
+    size_t par, occ, keys, sites, counts, prefix, parc, wpos, win, total;
 };
 
 Sizes plan_sizes(const Plan &p, int bucket_log2)
@@ -258,8 +258,12 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
     s.sites = align_up(static_cast<size_t>(nb_alloc) * s.cap * 4);
     s.counts = align_up(static_cast<size_t>(nb_alloc) * 4);
     s.prefix = align_up(static_cast<size_t>(s.prefix_cap) * 4);
+    // the bulk labelling's list forest and word positions (not for periodic
+    // first-wrap samples, whose labelling runs on the lattice entries)
+    s.parc = p.wrap ? 0 : align_up(static_cast<size_t>(s.prefix_cap) * 4);
+    s.wpos = (p.wrap || s.prefix_cap == 0) ? 0 : s.occ;
     s.win = p.win_hi > 0 ? align_up(static_cast<size_t>(p.win_hi - p.win_lo) * 4) : 0;
-    s.total = s.par + s.occ + s.keys + s.sites + s.counts + s.prefix + s.win;
+    s.total = s.par + s.occ + s.keys + s.sites + s.counts + s.prefix + s.parc + s.wpos + s.win;
     return s;
 }
 
@@ -497,6 +501,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 d.off_sites = off; off += s.sites;
                 d.off_counts = off; off += s.counts;
                 d.off_prefix = off; off += s.prefix;
+                d.off_parc = off; off += s.parc;
+                d.off_wpos = off; off += s.wpos;
                 d.off_win = off; off += s.win;
                 d.smax_mode = p.win_hi > 0 ? 1 : 0;
                 d.win_lo = static_cast<int32_t>(p.win_lo);

@@ -44,7 +44,9 @@ struct NzSample {
     uint64_t off_keys;
     uint64_t off_sites;
     uint64_t off_counts;
-    uint64_t off_prefix;
+    uint64_t off_prefix;  // prefilled sites in list order (site order within each key block)
+    uint64_t off_parc;    // parents of the list entries during the bulk labelling
+    uint64_t off_wpos;    // per bitset word: list position of its first prefilled site
     int32_t L;
     int32_t N;
     int32_t nb;           // buckets of the key band [T0, T0 + nb << shift)

@@ -201,12 +201,14 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
                                                                int32_t blocks_per_sample, uint8_t *__restrict__ ws,
                                                                NzState *__restrict__ state)
 {
-    // prefilled sites of this block, staged in LDS (one slice per wave, filled
-    // in ballot order without atomics) and appended to the sample's list with
-    // one global atomic per block
-    constexpr uint32_t kSlice = KEYS_SITES_PER_BLOCK / (KEYS_THREADS / 64);
-    __shared__ uint32_t pre_sites[KEYS_SITES_PER_BLOCK];
-    __shared__ uint32_t pre_count[KEYS_THREADS / 64];
+    // The prefilled sites of this block are appended to the sample's list in
+    // site order, with one global atomic per block: their bitset words are kept
+    // in LDS, scanned, and every word's list position is stored, so that a
+    // site's list position is that of its word plus the set bits below it.
+    constexpr uint32_t kWords = KEYS_SITES_PER_BLOCK / 32;
+    __shared__ uint32_t pre_words[kWords];
+    __shared__ uint32_t pre_excl[kWords];
+    __shared__ uint32_t pre_tot[2];
     __shared__ uint32_t pre_base;
     __shared__ uint64_t bq_key[KEYS_THREADS / 64][KEYS_BQ];
     __shared__ uint32_t bq_site[KEYS_THREADS / 64][KEYS_BQ];
@@ -232,6 +234,8 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
     c.counts = reinterpret_cast<uint32_t *>(ws + d.off_counts);
     uint32_t *occ = reinterpret_cast<uint32_t *>(ws + d.off_occ);
     uint32_t *prefix = reinterpret_cast<uint32_t *>(ws + d.off_prefix);
+    if (threadIdx.x < kWords) pre_words[threadIdx.x] = 0u;
+    __syncthreads();
     // keys in [T0, band_end) fall into the band (band_end saturates at 2^64)
     const uint64_t span = c.nb << c.shift;
     const bool band_all = c.shift >= 64 || (span >> c.shift) != c.nb || c.T0 + span < c.T0;
@@ -239,10 +243,8 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
 
     const uint32_t lane = lane_id();
     const uint32_t wave = threadIdx.x >> 6;
-    uint32_t *slice = pre_sites + wave * kSlice;
     uint64_t *qk = bq_key[wave];
     uint32_t *qs = bq_site[wave];
-    uint32_t nstaged = 0;   // wave-uniform
     uint32_t nq = 0;        // wave-uniform
     const uint32_t block_base = static_cast<uint32_t>(blk) * KEYS_SITES_PER_BLOCK;
     for (int it = 0; it < KEYS_ITERS; ++it) {
@@ -267,22 +269,10 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
         const uint32_t e16 = static_cast<uint32_t>(be >> (16u * q)) & 0xFFFFu;
         const uint32_t o16 = static_cast<uint32_t>(bo >> (16u * q)) & 0xFFFFu;
         const uint32_t widx = (wbase >> 5) + q;
-        if (widx < occ_words) occ[widx] = spread_even(e16) | (spread_even(o16) << 1);
-        // prefilled: parent = itself, staged even sites first, then odd
-        const uint32_t ne = static_cast<uint32_t>(__popcll(be));
-        if (pre0) {
-            if (d.wrap) reinterpret_cast<uint64_t *>(c.par)[i0] = i0;   // itself, displacement 0
-            else c.par[i0] = static_cast<int32_t>(i0);
-            slice[nstaged + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(be >> 32),
-                                                      __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(be), 0u))] = i0;
-        }
-        if (pre1) {
-            if (d.wrap) reinterpret_cast<uint64_t *>(c.par)[i1] = i1;
-            else c.par[i1] = static_cast<int32_t>(i1);
-            slice[nstaged + ne + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(bo >> 32),
-                                                           __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(bo), 0u))] = i1;
-        }
-        nstaged += ne + static_cast<uint32_t>(__popcll(bo));
+        const uint32_t word = spread_even(e16) | (spread_even(o16) << 1);
+        if (widx < occ_words) occ[widx] = word;
+        // the block's prefilled words, in site order (chunk it * 4 + wave)
+        if (lane < 4u) pre_words[(static_cast<uint32_t>(it) * 4u + wave) * 4u + q] = word;
         // band: queued, then bucketed in full waves
         const uint32_t nqe = static_cast<uint32_t>(__popcll(qe));
         if (band0) {
@@ -320,23 +310,50 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
         }
     }
     if (lane < nq) keys_bucket(c, qk[lane], qs[lane]);
-    if (lane == 0) pre_count[wave] = nstaged;
+    if (d.T0 == 0) return;   // plain sample: nothing prefilled (uniform over the block)
     __syncthreads();
-    uint32_t cnt = 0;
+    // exclusive scan of the 128 word counts (waves 0 and 1, one word per lane)
+    uint32_t wc = 0, incl = 0;
+    if (threadIdx.x < kWords) {
+        wc = static_cast<uint32_t>(__popc(pre_words[threadIdx.x]));
+        incl = wc;
 #pragma unroll
-    for (int w = 0; w < KEYS_THREADS / 64; ++w) cnt += pre_count[w];
-    if (cnt) {
-        if (threadIdx.x == 0) pre_base = atomicAdd(reinterpret_cast<uint32_t *>(&state[sid].n0), cnt);
-        __syncthreads();
-        uint32_t base = pre_base;
-        for (int w = 0; w < KEYS_THREADS / 64; ++w) {
-            const uint32_t n = pre_count[w];
-            for (uint32_t k = threadIdx.x; k < n; k += KEYS_THREADS) {
-                const uint32_t pos = base + k;
-                if (pos < static_cast<uint32_t>(d.prefix_cap)) prefix[pos] = pre_sites[w * kSlice + k];
-            }
-            base += n;
+        for (int o = 1; o < 64; o <<= 1) {
+            const uint32_t v = __shfl_up(incl, o);
+            if (lane >= static_cast<uint32_t>(o)) incl += v;
         }
+        if (lane == 63u) pre_tot[wave] = incl;
+    }
+    __syncthreads();
+    const uint32_t cnt = pre_tot[0] + pre_tot[1];
+    if (cnt == 0) return;
+    if (threadIdx.x < kWords) pre_excl[threadIdx.x] = incl - wc + (wave == 1u ? pre_tot[0] : 0u);
+    if (threadIdx.x == 0) pre_base = atomicAdd(reinterpret_cast<uint32_t *>(&state[sid].n0), cnt);
+    __syncthreads();
+    const uint32_t base = pre_base;
+    const uint32_t cap = static_cast<uint32_t>(d.prefix_cap);
+    const uint32_t w0 = block_base >> 5;
+    if (!d.wrap && threadIdx.x < kWords && w0 + threadIdx.x < occ_words) {
+        uint32_t *wpos = reinterpret_cast<uint32_t *>(ws + d.off_wpos);
+        wpos[w0 + threadIdx.x] = base + pre_excl[threadIdx.x];
+    }
+    // the sites: two threads per word, 16 bits each, in bit order
+    const uint32_t k = threadIdx.x >> 1, h = threadIdx.x & 1u;
+    const uint32_t wv = pre_words[k];
+    uint32_t bits = (wv >> (16u * h)) & 0xFFFFu;
+    uint32_t pos = base + pre_excl[k] + (h ? static_cast<uint32_t>(__popc(wv & 0xFFFFu)) : 0u);
+    const uint32_t site0 = block_base + k * 32u + 16u * h;
+    int32_t *parc = reinterpret_cast<int32_t *>(ws + d.off_parc);
+    while (bits) {
+        const uint32_t sidx = site0 + static_cast<uint32_t>(__builtin_ctz(bits));
+        bits &= bits - 1u;
+        if (pos < cap) {
+            prefix[pos] = sidx;
+            // parent = itself (periodic first-wrap: lattice entry, displacement 0)
+            if (d.wrap) reinterpret_cast<uint64_t *>(c.par)[sidx] = sidx;
+            else parc[pos] = static_cast<int32_t>(pos);
+        }
+        ++pos;
     }
 }
 
@@ -439,6 +456,13 @@ __device__ __forceinline__ bool xcd_slot(int32_t nlist, int32_t bx, int32_t &y, 
     return y < nlist;
 }
 
+// The bulk labelling runs on the prefilled sites' list positions, not on
+// lattice indices: parc[i] is the parent of list entry i, so the whole forest
+// of a sample is 4 bytes per prefilled site and stays in the L2 of the XCD that
+// holds the sample.  The list position of an occupied neighbour t is the
+// position of its bitset word (wpos) plus the set bits below t in that word.
+// The expand pass writes the lattice parent words the sweep reads.
+
 // Hook: one thread per prefilled site and its forward half of the offset
 // table (one of each +-d pair), eight neighbour words loaded at a time.
 constexpr int HOOK_UNROLL = 8;
@@ -457,8 +481,9 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
     const int32_t zh = d.z >> 1;
     const uint64_t magic = d.magic;
     const bool periodic = d.periodic != 0;
-    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
+    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_parc);
     const uint32_t *occ = reinterpret_cast<const uint32_t *>(ws + d.off_occ);
+    const uint32_t *wpos = reinterpret_cast<const uint32_t *>(ws + d.off_wpos);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
     const NzOffset *tab = tabs + d.tab;
     for (int32_t i = x * 256 + static_cast<int32_t>(threadIdx.x); i < n0; i += bx * 256) {
@@ -484,9 +509,11 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
             }
 #pragma unroll
             for (int q = 0; q < HOOK_UNROLL; ++q) {
+                const uint32_t below = w[q] & ((1u << (t[q] & 31)) - 1u);
                 if (!((w[q] >> (t[q] & 31)) & 1u)) continue;
-                if (u < 0) u = cc_find(par, s);
-                int32_t v = cc_find(par, t[q]);
+                const int32_t j = static_cast<int32_t>(wpos[static_cast<uint32_t>(t[q]) >> 5]) + __popc(below);
+                if (u < 0) u = cc_find(par, i);
+                int32_t v = cc_find(par, j);
                 while (u != v) {
                     const int32_t hi = max(u, v), lo = min(u, v);
                     int32_t expected = hi;
@@ -527,22 +554,21 @@ __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__rest
     const int32_t n0 = state[sid].n0;
     if (n0 > d.prefix_cap || d.wrap) return;
     const uint32_t L = static_cast<uint32_t>(d.L);
-    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
+    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_parc);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
     for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
-        const int32_t s = static_cast<int32_t>(prefix[k]);
-        int32_t r = s;
+        int32_t r = k;
         int32_t p = ld_w(&par[r]);
         while (p >= 0 && p != r) {
             r = p;
             p = ld_w(&par[r]);
         }
-        if (r == s) {
-            const uint32_t fl = d.periodic ? 0u : border_flags(static_cast<uint32_t>(s), L, d.magic);
-            st_w(&par[s], static_cast<int32_t>(NZ_ROOT | fl | 1u));
+        if (r == k) {
+            const uint32_t fl = d.periodic ? 0u : border_flags(prefix[k], L, d.magic);
+            st_w(&par[k], static_cast<int32_t>(NZ_ROOT | fl | 1u));
             if (fl == NZ_FLAGS) state[sid].status = NZ_ST_BACKOFF;   // L = 1: one site spans
         } else {
-            st_w(&par[s], r);
+            st_w(&par[k], r);
         }
     }
 }
@@ -566,20 +592,40 @@ __global__ __launch_bounds__(256) void nz_accum_kernel(const NzSample *__restric
         return;
     }
     const uint32_t L = static_cast<uint32_t>(d.L);
-    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
+    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_parc);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
     for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
-        const int32_t s = static_cast<int32_t>(prefix[k]);
-        const int32_t r = par[s];
+        const int32_t r = par[k];
         if (r >= 0) {
             uint32_t *root = reinterpret_cast<uint32_t *>(&par[r]);
             atomicAdd(root, 1u);
-            const uint32_t fl = d.periodic ? 0u : border_flags(static_cast<uint32_t>(s), L, d.magic);
+            const uint32_t fl = d.periodic ? 0u : border_flags(prefix[k], L, d.magic);
             if (fl) {
                 const uint32_t old = atomicOr(root, fl);
                 if (((old | fl) & NZ_FLAGS) == NZ_FLAGS && !d.smax_mode) state[sid].status = NZ_ST_BACKOFF;
             }
         }
+    }
+}
+
+// Expand: the lattice parent word of every prefilled site, from the list
+// forest (a root keeps its root word, a member points at its root's site).
+__global__ __launch_bounds__(256) void nz_expand_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
+                                                        int32_t nlist, int32_t bx, uint8_t *__restrict__ ws,
+                                                        NzState *__restrict__ state)
+{
+    int32_t y, x;
+    if (!xcd_slot(nlist, bx, y, x)) return;
+    const int sid = list[y];
+    const NzSample &d = desc[sid];
+    const int32_t n0 = state[sid].n0;
+    if (n0 > d.prefix_cap || d.wrap) return;
+    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
+    const int32_t *parc = reinterpret_cast<const int32_t *>(ws + d.off_parc);
+    const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
+    for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
+        const int32_t v = parc[k];
+        par[prefix[k]] = v < 0 ? v : static_cast<int32_t>(prefix[v]);
     }
 }
 
@@ -596,11 +642,10 @@ __global__ __launch_bounds__(256) void nz_rootmax_kernel(const NzSample *__restr
     if (!d.smax_mode) return;
     const int32_t n0 = state[sid].n0;
     if (n0 > d.prefix_cap) return;
-    const int32_t *par = reinterpret_cast<const int32_t *>(ws + d.off_par);
-    const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
+    const int32_t *par = reinterpret_cast<const int32_t *>(ws + d.off_parc);
     int32_t best = 0;
     for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
-        const int32_t v = par[prefix[k]];
+        const int32_t v = par[k];
         if (v < 0) best = max(best, static_cast<int32_t>(static_cast<uint32_t>(v) & NZ_SIZE));
     }
     if (best > 0) atomicMax(&state[sid].smax, best);
@@ -1781,6 +1826,8 @@ hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nli
                        nlist, bx_site, ws, state);
     hipLaunchKernelGGL(nz_accum_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list, nlist,
                        bx_site, ws, state);
+    hipLaunchKernelGGL(nz_expand_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
+                       nlist, bx_site, ws, state);
     if (smax)
         hipLaunchKernelGGL(nz_rootmax_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
                            nlist, bx_site, ws, state);
