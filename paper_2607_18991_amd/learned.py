@@ -98,7 +98,7 @@ class PrefillModel:
         out = y.cpu().numpy().astype(np.float64)
         return np.exp(out[:, 0]), np.exp(out[:, 1])
 
-    def plan(self, jobs, k_sigma: float = 3.0, band_sigma: float = 8.0):
+    def plan(self, jobs, k_sigma: float = 3.0, band_sigma: float = 5.0):
         """Copies of the job dicts with the learned n0, backoff step and band."""
         jobs = [dict(j) for j in jobs]
         mean, std = self.predict([j["zone_mask"] for j in jobs], [j["L"] for j in jobs])
@@ -111,7 +111,7 @@ class PrefillModel:
         return jobs
 
 
-def plan_band_only(model: PrefillModel, jobs, band_sigma: float = 8.0):
+def plan_band_only(model: PrefillModel, jobs, band_sigma: float = 5.0):
     """Plain sweeps (no prefill) with the learned band size, so that plain and
     learned runs differ only in the prefill."""
     mean, std = model.predict([j["zone_mask"] for j in jobs], [j["L"] for j in jobs])
