@@ -174,6 +174,9 @@ size_t align_up(size_t v) { return (v + kAlign - 1) / kAlign * kAlign; }
 // c ~ 1.553, b ~ 1.01); used only to size key bands and to order work.
 double pc_prior(int z) { return 1.553 / (z + 1.01); }
 
+// 32-bit words of a sample's bitset summary in the sweep's LDS slice
+constexpr int64_t kSumWords = 1024;
+
 struct Plan {
     int32_t job;
     int64_t sample;      // Philox sample index
@@ -205,7 +208,8 @@ struct Sizes {
     int64_t n0b[2];
     uint64_t T0b[2];
     int32_t nbb[2];
-    size_t par, occ, keys, sites, counts, prefix, parc, wpos, win, total;
+    size_t par, occ, keys, sites, counts, prefix, parc, wpos, win, sum, total;
+    int32_t sum_shift, sum_words;
 };
 
 Sizes plan_sizes(const Plan &p, int bucket_log2)
@@ -263,7 +267,17 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
     s.parc = p.wrap ? 0 : align_up(static_cast<size_t>(s.prefix_cap) * 4);
     s.wpos = (p.wrap || s.prefix_cap == 0) ? 0 : s.occ;
     s.win = p.win_hi > 0 ? align_up(static_cast<size_t>(p.win_hi - p.win_lo) * 4) : 0;
-    s.total = s.par + s.occ + s.keys + s.sites + s.counts + s.prefix + s.parc + s.wpos + s.win;
+    // bitset summary for the HBM-resident sweep: at most kSumWords words, one
+    // bit per 1..16 bitset words (none above that: L > 27, or first-wrap samples)
+    {
+        const int64_t words = (N + 63) / 64 * 2;
+        int gs = 0;
+        while (((words >> gs) + 31) / 32 > kSumWords) ++gs;
+        s.sum_shift = gs;
+        s.sum_words = (gs <= 4 && !p.wrap) ? static_cast<int32_t>(((words >> gs) + 31) / 32 + 1) : 0;
+        s.sum = align_up(static_cast<size_t>(s.sum_words) * 4);
+    }
+    s.total = s.par + s.occ + s.keys + s.sites + s.counts + s.prefix + s.parc + s.wpos + s.win + s.sum;
     return s;
 }
 
@@ -472,7 +486,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             std::vector<int32_t> out_index(n), queue(n), prefill_list;
             std::vector<int32_t> chunk_of_desc(n);
             size_t off = head;
-            int32_t max_nb = 0, max_cap = 0, max_z = 0;
+            int32_t max_nb = 0, max_cap = 0, max_z = 0, max_sum = 0;
             uint32_t max_N = 0;
             int64_t max_site = 0;
             std::vector<int32_t> desc_of_chunk(n);
@@ -503,6 +517,9 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 d.off_prefix = off; off += s.prefix;
                 d.off_parc = off; off += s.parc;
                 d.off_wpos = off; off += s.wpos;
+                d.off_sum = off; off += s.sum;
+                d.sum_shift = s.sum_shift;
+                d.sum_words = s.sum_words;
                 d.off_win = off; off += s.win;
                 d.smax_mode = p.win_hi > 0 ? 1 : 0;
                 d.win_lo = static_cast<int32_t>(p.win_lo);
@@ -515,6 +532,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 max_nb = std::max(max_nb, d.nb);
                 max_cap = std::max(max_cap, d.cap);
                 max_z = std::max(max_z, d.z);
+                max_sum = std::max(max_sum, d.sum_words);
                 max_N = std::max(max_N, static_cast<uint32_t>(d.N));
                 if (d.T0 != 0) {
                     prefill_list.push_back(di);
@@ -630,7 +648,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             } else {
                 int residency = tune.residency == 3 ? 2 : (tune.residency == 1 ? 1 : 0);
                 const uint32_t occ_words = ((max_N + 63) / 64) * 2;
-                uint32_t lds_words = residency == 2 ? occ_words + max_N : (residency == 1 ? occ_words : 0);
+                // HBM residency: the slice starts with the samples' bitset summaries
+                uint32_t lds_words = residency == 2 ? occ_words + max_N : (residency == 1 ? occ_words : static_cast<uint32_t>(max_sum));
                 // sweep mode: 2 = 64 sites per step for every sample; auto = 64 sites per
                 // step for z <= 512 (wider neighbourhoods are faster one site at a time)
                 int32_t min_z = 1 << 30;

@@ -65,6 +65,9 @@ struct NzSample {
     int32_t wrap;         // 1: periodic first-wrap sweep; entries of off_par are 64-bit
                           //    (low half the parent word, high half the x0 displacement
                           //    from the parent)
+    uint64_t off_sum;     // bitset summary: bit k set unless words k << sum_shift .. are all zero
+    int32_t sum_shift;
+    int32_t sum_words;    // 32-bit summary words (0: no summary)
 };
 
 // Per-sample result/state record written by the kernels.

@@ -137,6 +137,8 @@ __global__ __launch_bounds__(256) void nz_clear_kernel(const NzSample *__restric
     const NzSample &d = desc[sid];
     uint32_t *counts = reinterpret_cast<uint32_t *>(ws + d.off_counts);
     for (int b = threadIdx.x; b < d.nb; b += blockDim.x) counts[b] = 0u;
+    uint32_t *sum = reinterpret_cast<uint32_t *>(ws + d.off_sum);
+    for (int w = threadIdx.x; w < d.sum_words; w += blockDim.x) sum[w] = 0u;
     if (threadIdx.x == 0) {
         NzState s;
         s.status = NZ_ST_PENDING;
@@ -323,6 +325,25 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
             if (lane >= static_cast<uint32_t>(o)) incl += v;
         }
         if (lane == 63u) pre_tot[wave] = incl;
+    }
+    // summary bits of the block's non-empty words (one or two atomics per wave)
+    if (threadIdx.x < kWords && d.sum_words > 0) {
+        const uint64_t nz = __ballot(wc != 0u);
+        const uint32_t gs = static_cast<uint32_t>(d.sum_shift);
+        const uint32_t wfirst = (block_base >> 5) + wave * 64u;   // a multiple of 64
+        uint32_t *sum = reinterpret_cast<uint32_t *>(ws + d.off_sum);
+        if (gs == 0u) {
+            const uint32_t half = lane < 2u ? static_cast<uint32_t>(nz >> (32u * lane)) : 0u;
+            if (half) atomicOr(&sum[(wfirst >> 5) + lane], half);
+        } else if (lane == 0u && nz) {
+            // bit j of v: any of the 2^gs words j << gs .. of this wave (gs <= 4)
+            const uint32_t span = 64u >> gs;
+            uint32_t v = 0u;
+            for (uint32_t j = 0; j < span; ++j)
+                if ((nz >> (j << gs)) & ((1ull << (1u << gs)) - 1ull)) v |= 1u << j;
+            const uint32_t k = wfirst >> gs;
+            atomicOr(&sum[k >> 5], v << (k & 31));
+        }
     }
     __syncthreads();
     const uint32_t cnt = pre_tot[0] + pre_tot[1];
@@ -676,30 +697,62 @@ __global__ __launch_bounds__(256) void nz_winsum_kernel(const NzSample *__restri
 
 enum { RES_HBM = 0, RES_OCC = 1, RES_ALL = 2 };
 
+// With the bitset in HBM, the wave's LDS slice starts with a summary of it:
+// bit k is clear only if bitset words k << sshift .. ((k + 1) << sshift) - 1
+// are all zero.  An occupancy check reads the summary first and fetches the
+// word from HBM only when its bit is set; near the threshold most words of a
+// wide neighbourhood's lattice are empty.  Bits are set when sites are added
+// and never cleared (a stale set bit only costs a load).
 template <int RES>
 struct SweepMem {
     uint32_t *occ_g;
     int32_t *par_g;
     uint32_t lbase;     // first LDS word of this wave's slice
     uint32_t occ_words; // bitset words (padded to 64 sites)
+    uint32_t sshift;    // summary: log2 of bitset words per bit
+    bool sum_on;        // the summary is in use (RES_HBM only)
 
+    __device__ __forceinline__ bool maybe(uint32_t *lds, uint32_t w) const
+    {
+        if constexpr (RES != RES_HBM) return true;
+        if (!sum_on) return true;
+        const uint32_t k = w >> sshift;
+        return (ld_w(&lds[lbase + (k >> 5)]) >> (k & 31)) & 1u;
+    }
+    __device__ __forceinline__ void mark(uint32_t *lds, uint32_t w) const
+    {
+        if constexpr (RES == RES_HBM) {
+            if (sum_on) {
+                const uint32_t k = w >> sshift;
+                __hip_atomic_fetch_or(&lds[lbase + (k >> 5)], 1u << (k & 31), __ATOMIC_RELAXED,
+                                      __HIP_MEMORY_SCOPE_WAVEFRONT);
+            }
+        }
+    }
     __device__ __forceinline__ uint32_t occ_ld(uint32_t *lds, uint32_t w) const
     {
-        if constexpr (RES == RES_HBM) return ld_w(&occ_g[w]);
+        if constexpr (RES == RES_HBM) return maybe(lds, w) ? ld_w(&occ_g[w]) : 0u;
         else return ld_w(&lds[lbase + w]);
     }
+    // called by every lane with the same word and value
     __device__ __forceinline__ void occ_st(uint32_t *lds, uint32_t w, uint32_t v) const
     {
-        if constexpr (RES == RES_HBM) st_w(&occ_g[w], v);
-        else st_w(&lds[lbase + w], v);
+        if constexpr (RES == RES_HBM) {
+            st_w(&occ_g[w], v);
+            if (lane_id() == 0) mark(lds, w);
+        } else {
+            st_w(&lds[lbase + w], v);
+        }
     }
     // several lanes may set bits of one word at once
     __device__ __forceinline__ void occ_or(uint32_t *lds, uint32_t w, uint32_t bits) const
     {
-        if constexpr (RES == RES_HBM)
+        if constexpr (RES == RES_HBM) {
             __hip_atomic_fetch_or(&occ_g[w], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
-        else
+            mark(lds, w);
+        } else {
             __hip_atomic_fetch_or(&lds[lbase + w], bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+        }
     }
     __device__ __forceinline__ void occ_andn(uint32_t *lds, uint32_t w, uint32_t bits) const
     {
@@ -1208,6 +1261,14 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         m.par_g = reinterpret_cast<int32_t *>(a.ws + d.off_par);
         m.lbase = wave * a.lds_words;
         m.occ_words = static_cast<uint32_t>(((N + 63) >> 6) << 1);
+        m.sshift = static_cast<uint32_t>(d.sum_shift);
+        m.sum_on = false;
+        if constexpr (RES == RES_HBM) {
+            m.sum_on = d.sum_words > 0;
+            const uint32_t *sum_g = reinterpret_cast<const uint32_t *>(a.ws + d.off_sum);
+            for (int32_t w = lane; w < d.sum_words; w += 64) lds[m.lbase + w] = sum_g[w];
+            __builtin_amdgcn_wave_barrier();
+        }
         if constexpr (RES != RES_HBM) {
             for (uint32_t w = lane; w < m.occ_words; w += 64) lds[m.lbase + w] = prefilled ? m.occ_g[w] : 0u;
             if constexpr (RES == RES_ALL) {
@@ -1711,6 +1772,8 @@ __global__ __launch_bounds__(256) void nz_wrap_sweep_kernel(NzSweepArgs a, Sweep
         m.par_g = nullptr;   // the occupancy side only; entries go through pw
         m.lbase = 0;
         m.occ_words = 0;
+        m.sshift = 0;
+        m.sum_on = false;   // no summary: every check reads the bitset
         uint64_t *pw = reinterpret_cast<uint64_t *>(a.ws + d.off_par);
         const NzOffset *tab = a.tabs + d.tab;
         int32_t ostride[NCH], od0[NCH];
