@@ -1110,6 +1110,11 @@ __device__ __forceinline__ int block_step(const SweepMem<RES> &m, uint32_t *lds,
     int32_t pv[BLK_K];
 #pragma unroll
     for (int k = 0; k < BLK_K; ++k) pv[k] = (!bad && k < cntn) ? m.par_ld(lds, nl[k]) : -1;
+    // the first hop of every find, issued together (a prefilled site points
+    // straight at its root, so this usually reaches it)
+    int32_t gv[BLK_K];
+#pragma unroll
+    for (int k = 0; k < BLK_K; ++k) gv[k] = (!bad && k < cntn && pv[k] >= 0 && pv[k] < BLK_MARK) ? m.par_ld(lds, pv[k]) : -1;
     int nnew = 0;
 #pragma unroll
     for (int k = 0; k < BLK_K; ++k) {
@@ -1120,7 +1125,16 @@ __device__ __forceinline__ int block_step(const SweepMem<RES> &m, uint32_t *lds,
             } else {
                 int32_t root;
                 uint32_t word;
-                sweep_find_from<RES>(m, lds, nl[k], pv[k], root, word);
+                if (pv[k] < 0) {
+                    root = nl[k];
+                    word = static_cast<uint32_t>(pv[k]);
+                } else if (gv[k] < 0) {
+                    root = pv[k];
+                    word = static_cast<uint32_t>(gv[k]);
+                } else {
+                    m.par_st(lds, nl[k], gv[k]);   // halving: the neighbour skips to its grandparent
+                    sweep_find<RES>(m, lds, gv[k], root, word);
+                }
                 uint32_t h = blk_hash(static_cast<uint32_t>(root));
                 int slot = -1;
                 for (uint32_t t = 0; t < BLK_RSLOTS; ++t) {
@@ -1349,38 +1363,58 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
             }
             SiteStep<NCH> cur;
             bool done = false;
-            for (int32_t b = 0; b < nb && !done; ++b) {
-                const uint32_t cnt = counts[b];
-                if (cnt > cap) {
-                    status = NZ_ST_BUCKET;
-                    break;
+            // Block cursor over the band: bucket cb, offset cj of the next block.
+            // A block's sites are loaded one block ahead, so that load overlaps
+            // the previous block's step.  1: pc holds the block's sites (lanes
+            // < n); 0: end of the band; -1: an over-full bucket was reached.
+            int32_t cb = 0;
+            uint32_t cj = 0;
+            uint32_t ccnt = nb > 0 ? counts[0] : 0u;
+            auto next_block = [&](uint32_t &pc, int &n) -> int {
+                while (cb < nb && cj >= ccnt) {
+                    ++cb;
+                    cj = 0;
+                    if (cb < nb) ccnt = counts[cb];
                 }
-                const uint32_t *bs = sites + static_cast<uint64_t>(b) * cap;
-                for (uint32_t j0 = 0; j0 < cnt; j0 += 64) {
-                    const int nbk = static_cast<int>(min(64u, cnt - j0));
-                    const uint32_t pcl = static_cast<int>(lane) < nbk ? bs[j0 + lane] : 0u;
-                    const int res = block_step<RES>(m, lds, hbase, nbk, pcl, L, tab, off0, z, a.blk_old);
-                    if (res == BLK_FALLBACK) {
-                        load_offsets();
-                        for (int i = 0; i < nbk; ++i) {
-                            ++r;
-                            cur.prepare(m, lds, bcast(pcl, i), L, ostride, ocode);
-                            uint32_t total, flags;
-                            sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
-                            if (flags == NZ_FLAGS) {
-                                status = NZ_ST_DONE;
-                                nstar = r;
-                                mass = static_cast<int32_t>(total);
-                                done = true;
-                                break;
-                            }
+                if (cb >= nb) return 0;
+                if (ccnt > cap) return -1;
+                n = static_cast<int>(min(64u, ccnt - cj));
+                pc = static_cast<int>(lane) < n ? sites[static_cast<uint64_t>(cb) * cap + cj + lane] : 0u;
+                cj += 64u;
+                return 1;
+            };
+            uint32_t pcl = 0;
+            int nbk = 0;
+            int got = next_block(pcl, nbk);
+            while (got == 1) {
+                uint32_t pcn = 0;
+                int nbn = 0;
+                const int gotn = next_block(pcn, nbn);
+                const int res = block_step<RES>(m, lds, hbase, nbk, pcl, L, tab, off0, z, a.blk_old);
+                if (res == BLK_FALLBACK) {
+                    load_offsets();
+                    for (int i = 0; i < nbk; ++i) {
+                        ++r;
+                        cur.prepare(m, lds, bcast(pcl, i), L, ostride, ocode);
+                        uint32_t total, flags;
+                        sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
+                        if (flags == NZ_FLAGS) {
+                            status = NZ_ST_DONE;
+                            nstar = r;
+                            mass = static_cast<int32_t>(total);
+                            done = true;
+                            break;
                         }
-                        if (done) break;
-                        continue;
                     }
+                    if (done) break;
+                } else {
                     r += nbk;
                 }
+                got = gotn;
+                pcl = pcn;
+                nbk = nbn;
             }
+            if (!done && got < 0) status = NZ_ST_BUCKET;
         } else {
         load_offsets();
         // The band in (key, site) order; the occupancy words of the next site are
