@@ -679,7 +679,12 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 args.dcap = tune.dcap;
                 args.blk_old = env_blk_old();
                 args.blk_zmax = blk_zmax;
-                HIP_TRY(nz::launch_sweep(nch_for(max_z), residency, block, args, d_nstar, d_mass, d_outidx, grid, wg_waves, st));
+                // the block path's fallback needs more than 8 offset chunks only
+                // when a sample wider than z = 512 goes 64 sites per step
+                bool wide_block = false;
+                for (const NzSample &d : desc) wide_block = wide_block || (block && d.z > 512 && d.z <= blk_zmax && !d.smax_mode);
+                HIP_TRY(nz::launch_sweep(nch_for(max_z), wide_block, residency, block, args, d_nstar, d_mass, d_outidx, grid,
+                                         wg_waves, st));
             }
             if (smax)
                 HIP_TRY(nz::launch_winsum(d_desc, d_state, n, static_cast<int32_t>(smax->win_hi - smax->win_lo), ws,

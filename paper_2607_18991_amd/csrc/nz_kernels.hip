@@ -885,9 +885,23 @@ struct SiteStep {
     int32_t s;
     uint32_t fl;
     uint32_t own;
-    uint32_t word[NCH];
-    int32_t tn[NCH];
-    bool inb[NCH];
+    uint32_t A;          // allowed axes of s
+    bool per;            // periodic boundaries
+    uint32_t word[NCH];  // 0 for a neighbour outside the lattice
+
+    // Neighbour c of s (recomputed rather than held: one register per chunk
+    // less, which keeps wide-neighbourhood kernels at more waves per SIMD).
+    __device__ __forceinline__ int32_t nbr(int c, const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH],
+                                           int32_t L) const
+    {
+        const uint32_t out = ocode[c] & ~A;
+        return s + ostride[c] + (per && out ? wrap_fix(out, L) : 0);
+    }
+    // neighbour c lies inside the lattice (or wraps, under periodic boundaries)
+    __device__ __forceinline__ bool inside(int c, const uint32_t (&ocode)[NCH]) const
+    {
+        return (ocode[c] & ~A) == 0u || (per && (ocode[c] & ~kCodeBits) == 0u);
+    }
 
     template <int RES>
     __device__ __forceinline__ void prepare(const SweepMem<RES> &m, uint32_t *lds, uint32_t pc, int32_t L,
@@ -896,27 +910,24 @@ struct SiteStep {
     {
         const int32_t x0 = pc & 63, x1 = (pc >> 6) & 63, x2 = (pc >> 12) & 63, x3 = (pc >> 18) & 63, x4 = pc >> 24;
         s = x0 + L * (x1 + L * (x2 + L * (x3 + L * x4)));
-        const uint32_t A = allowed_axis(x0, L) | (allowed_axis(x1, L) << 5) | (allowed_axis(x2, L) << 10) |
-                           (allowed_axis(x3, L) << 15) | (allowed_axis(x4, L) << 20);
+        A = allowed_axis(x0, L) | (allowed_axis(x1, L) << 5) | (allowed_axis(x2, L) << 10) |
+            (allowed_axis(x3, L) << 15) | (allowed_axis(x4, L) << 20);
+        per = periodic;
         fl = periodic ? 0u : ((x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u));
         own = m.occ_ld(lds, static_cast<uint32_t>(s) >> 5);
 #pragma unroll
-        for (int c = 0; c < NCH; ++c) {
-            const uint32_t out = ocode[c] & ~A;
-            inb[c] = out == 0u || (periodic && (ocode[c] & ~kCodeBits) == 0u);
-            tn[c] = s + ostride[c] + (periodic && out ? wrap_fix(out, L) : 0);
-            word[c] = inb[c] ? m.occ_ld(lds, static_cast<uint32_t>(tn[c]) >> 5) : 0u;
-        }
+        for (int c = 0; c < NCH; ++c)
+            word[c] = inside(c, ocode) ? m.occ_ld(lds, static_cast<uint32_t>(nbr(c, ostride, ocode, L)) >> 5) : 0u;
     }
 
     // Account for site p, occupied after these words were loaded.
-    __device__ __forceinline__ void patch(int32_t p)
+    __device__ __forceinline__ void patch(int32_t p, const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH], int32_t L)
     {
         const uint32_t bit = 1u << (p & 31);
         if ((s >> 5) == (p >> 5)) own |= bit;
 #pragma unroll
         for (int c = 0; c < NCH; ++c)
-            if (inb[c] && tn[c] == p) word[c] |= bit;
+            if (inside(c, ocode) && nbr(c, ostride, ocode, L) == p) word[c] |= bit;
     }
 };
 
@@ -931,8 +942,9 @@ constexpr bool kLookahead = NCH <= 2;
 // site itself), and merge them into the largest.  Returns the merged cluster's
 // size and border flags.
 template <int NCH, int RES>
-__device__ __forceinline__ void sweep_step(const SweepMem<RES> &m, uint32_t *lds, const SiteStep<NCH> &cur, int dcap,
-                                           uint32_t &total, uint32_t &flags)
+__device__ __forceinline__ void sweep_step(const SweepMem<RES> &m, uint32_t *lds, const SiteStep<NCH> &cur,
+                                           const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH], int32_t L,
+                                           int dcap, uint32_t &total, uint32_t &flags)
 {
     const uint32_t lane = lane_id();
     const int32_t s = cur.s;
@@ -945,12 +957,13 @@ __device__ __forceinline__ void sweep_step(const SweepMem<RES> &m, uint32_t *lds
     int D = 1;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-        const bool o = cur.inb[c] && ((cur.word[c] >> (cur.tn[c] & 31)) & 1u);
+        const int32_t t = cur.nbr(c, ostride, ocode, L);
+        const bool o = (cur.word[c] >> (t & 31)) & 1u;   // the word is 0 outside the lattice
         uint64_t mk = __ballot(o);
         if (!mk) continue;
         int32_t root = 0;
         uint32_t rw = 0;
-        if (o) sweep_find<RES>(m, lds, cur.tn[c], root, rw);
+        if (o) sweep_find<RES>(m, lds, t, root, rw);
         bool stale = false;   // a flush since these finds may have linked their roots
         while (mk) {
             const int l = __builtin_ctzll(mk);
@@ -1241,7 +1254,11 @@ struct SweepOut {
     const int32_t *out_index; // per sample: position in the caller's output arrays
 };
 
-template <int NCH, int RES, bool BLOCK>
+// NCH: offset chunks of one-site steps; FB: offset chunks of the block
+// sweep's one-site fallback (z <= 64 * FB for every block sample), kept
+// separate so that a launch whose wide neighbourhoods go one site at a time
+// does not carry their registers through the block path.
+template <int NCH, int RES, bool BLOCK, int FB>
 __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
 {
     extern __shared__ uint32_t lds[];
@@ -1297,14 +1314,15 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         // offset c * 64 + lane of the table per lane, for one-site-at-a-time steps
         int32_t ostride[NCH];
         uint32_t ocode[NCH];
+        // (relaxed atomic loads: kept where they are rather than hoisted out of
+        // the block loop, where the arrays would hold registers for every block)
         auto load_offsets = [&]() {
 #pragma unroll
             for (int c = 0; c < NCH; ++c) {
                 const int32_t j = c * 64 + static_cast<int32_t>(lane);
                 if (j < z) {
-                    const NzOffset o = tab[j];
-                    ostride[c] = o.stride;
-                    ocode[c] = o.code;
+                    ostride[c] = ld_w(&tab[j].stride);
+                    ocode[c] = ld_w(&tab[j].code);
                 } else {
                     ostride[c] = 0;
                     ocode[c] = 0xFFFFFFFFu;   // never inside: bits above 25 are never allowed
@@ -1361,7 +1379,9 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
                 off0[q].code = 0xFFFFFFFFu;
                 if (q < z) off0[q] = tab[q];
             }
-            SiteStep<NCH> cur;
+            SiteStep<FB> cur;
+            int32_t fstride[FB];
+            uint32_t fcode[FB];
             bool done = false;
             // Block cursor over the band: bucket cb, offset cj of the next block.
             // A block's sites are loaded one block ahead, so that load overlaps
@@ -1392,12 +1412,17 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
                 const int gotn = next_block(pcn, nbn);
                 const int res = block_step<RES>(m, lds, hbase, nbk, pcl, L, tab, off0, z, a.blk_old);
                 if (res == BLK_FALLBACK) {
-                    load_offsets();
+#pragma unroll
+                    for (int c = 0; c < FB; ++c) {
+                        const int32_t j = c * 64 + static_cast<int32_t>(lane);
+                        fstride[c] = j < z ? ld_w(&tab[j].stride) : 0;
+                        fcode[c] = j < z ? ld_w(&tab[j].code) : 0xFFFFFFFFu;
+                    }
                     for (int i = 0; i < nbk; ++i) {
                         ++r;
-                        cur.prepare(m, lds, bcast(pcl, i), L, ostride, ocode);
+                        cur.prepare(m, lds, bcast(pcl, i), L, fstride, fcode);
                         uint32_t total, flags;
-                        sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
+                        sweep_step<FB, RES>(m, lds, cur, fstride, fcode, L, dcap, total, flags);
                         if (flags == NZ_FLAGS) {
                             status = NZ_ST_DONE;
                             nstar = r;
@@ -1435,13 +1460,13 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
                 const int gotn = bc.next(pcn, lane);
                 if (gotn == 1) nxt.prepare(m, lds, pcn, L, ostride, ocode, periodic);
                 uint32_t total, flags;
-                sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
+                sweep_step<NCH, RES>(m, lds, cur, ostride, ocode, L, dcap, total, flags);
                 if (finished(total, flags)) break;
                 if (gotn != 1) {
                     if (gotn < 0) status = NZ_ST_BUCKET;
                     break;
                 }
-                nxt.patch(cur.s);
+                nxt.patch(cur.s, ostride, ocode, L);
                 cur = nxt;
             }
         } else {
@@ -1449,7 +1474,7 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
                 ++r;
                 cur.prepare(m, lds, pc, L, ostride, ocode, periodic);
                 uint32_t total, flags;
-                sweep_step<NCH, RES>(m, lds, cur, dcap, total, flags);
+                sweep_step<NCH, RES>(m, lds, cur, ostride, ocode, L, dcap, total, flags);
                 if (finished(total, flags)) break;
                 got = bc.next(pc, lane);
                 if (got < 0) status = NZ_ST_BUCKET;
@@ -1725,6 +1750,7 @@ __device__ __forceinline__ int32_t wrap_merge(uint64_t *pw, int D, int32_t lroot
 // compared whenever two neighbours share a root.
 template <int NCH>
 __device__ __forceinline__ void wrap_step(uint32_t *occ, uint64_t *pw, const SiteStep<NCH> &cur, const int32_t (&od0)[NCH],
+                                          const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH], int32_t L,
                                           int dcap, uint32_t &total, uint32_t &flags)
 {
     const uint32_t lane = lane_id();
@@ -1737,12 +1763,13 @@ __device__ __forceinline__ void wrap_step(uint32_t *occ, uint64_t *pw, const Sit
     int D = 1;
 #pragma unroll
     for (int c = 0; c < NCH; ++c) {
-        const bool o = cur.inb[c] && ((cur.word[c] >> (cur.tn[c] & 31)) & 1u);
+        const int32_t t = cur.nbr(c, ostride, ocode, L);
+        const bool o = (cur.word[c] >> (t & 31)) & 1u;   // the word is 0 outside the lattice
         uint64_t mk = __ballot(o);
         if (!mk) continue;
         int32_t root = 0, disp = 0;
         uint32_t rw = 0;
-        if (o) wrap_find(pw, cur.tn[c], root, rw, disp);
+        if (o) wrap_find(pw, t, root, rw, disp);
         // t = s + d: x0(s) - x0(root) = disp - d0
         const int32_t q = disp - od0[c];
         bool stale = false;   // a flush since these finds may have linked their roots
@@ -1833,7 +1860,7 @@ __global__ __launch_bounds__(256) void nz_wrap_sweep_kernel(NzSweepArgs a, Sweep
             ++r;
             cur.prepare(m, nullptr, pc, L, ostride, ocode, true);
             uint32_t total, flags;
-            wrap_step<NCH>(m.occ_g, pw, cur, od0, a.dcap, total, flags);
+            wrap_step<NCH>(m.occ_g, pw, cur, od0, ostride, ocode, L, a.dcap, total, flags);
             if (flags == NZ_FLAGS) {
                 status = NZ_ST_DONE;
                 nstar = r;
@@ -1941,11 +1968,11 @@ hipError_t launch_winsum(const NzSample *desc, const NzState *state, int32_t nsa
     return hipGetLastError();
 }
 
-template <int NCH, int RES, bool BLOCK>
+template <int NCH, int RES, bool BLOCK, int FB = NCH>
 static hipError_t launch_sweep_t(const NzSweepArgs &a, const SweepOut &o, int grid, int wg_waves, size_t lds,
                                  hipStream_t st)
 {
-    auto k = nz_sweep_kernel<NCH, RES, BLOCK>;
+    auto k = nz_sweep_kernel<NCH, RES, BLOCK, FB>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(lds));
@@ -1956,15 +1983,19 @@ static hipError_t launch_sweep_t(const NzSweepArgs &a, const SweepOut &o, int gr
 }
 
 template <int RES, bool BLOCK>
-static hipError_t launch_sweep_r(int nch, const NzSweepArgs &a, const SweepOut &o, int grid, int wg_waves, size_t lds,
-                                 hipStream_t st)
+static hipError_t launch_sweep_r(int nch, bool wide_block, const NzSweepArgs &a, const SweepOut &o, int grid,
+                                 int wg_waves, size_t lds, hipStream_t st)
 {
     switch (nch) {
     case 1: return launch_sweep_t<1, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
     case 2: return launch_sweep_t<2, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
     case 4: return launch_sweep_t<4, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
     case 8: return launch_sweep_t<8, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
-    case 14: return launch_sweep_t<14, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
+    case 14:
+        if constexpr (BLOCK) {
+            if (!wide_block) return launch_sweep_t<14, RES, BLOCK, 8>(a, o, grid, wg_waves, lds, st);
+        }
+        return launch_sweep_t<14, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -1986,23 +2017,23 @@ hipError_t launch_wrap_sweep(int nch, const NzSweepArgs &a, int32_t *nstar, int3
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int nch, int residency, bool block, const NzSweepArgs &a, int32_t *nstar, int32_t *mass,
-                        const int32_t *out_index, int grid, int wg_waves, hipStream_t st)
+hipError_t launch_sweep(int nch, bool wide_block, int residency, bool block, const NzSweepArgs &a, int32_t *nstar,
+                        int32_t *mass, const int32_t *out_index, int grid, int wg_waves, hipStream_t st)
 {
     SweepOut o{nstar, mass, out_index};
     const size_t lds = static_cast<size_t>(a.lds_words) * 4u * static_cast<size_t>(wg_waves);
     if (block) {
         switch (residency) {
-        case RES_HBM: return launch_sweep_r<RES_HBM, true>(nch, a, o, grid, wg_waves, lds, st);
-        case RES_OCC: return launch_sweep_r<RES_OCC, true>(nch, a, o, grid, wg_waves, lds, st);
-        case RES_ALL: return launch_sweep_r<RES_ALL, true>(nch, a, o, grid, wg_waves, lds, st);
+        case RES_HBM: return launch_sweep_r<RES_HBM, true>(nch, wide_block, a, o, grid, wg_waves, lds, st);
+        case RES_OCC: return launch_sweep_r<RES_OCC, true>(nch, wide_block, a, o, grid, wg_waves, lds, st);
+        case RES_ALL: return launch_sweep_r<RES_ALL, true>(nch, wide_block, a, o, grid, wg_waves, lds, st);
         default: return hipErrorInvalidValue;
         }
     }
     switch (residency) {
-    case RES_HBM: return launch_sweep_r<RES_HBM, false>(nch, a, o, grid, wg_waves, lds, st);
-    case RES_OCC: return launch_sweep_r<RES_OCC, false>(nch, a, o, grid, wg_waves, lds, st);
-    case RES_ALL: return launch_sweep_r<RES_ALL, false>(nch, a, o, grid, wg_waves, lds, st);
+    case RES_HBM: return launch_sweep_r<RES_HBM, false>(nch, wide_block, a, o, grid, wg_waves, lds, st);
+    case RES_OCC: return launch_sweep_r<RES_OCC, false>(nch, wide_block, a, o, grid, wg_waves, lds, st);
+    case RES_ALL: return launch_sweep_r<RES_ALL, false>(nch, wide_block, a, o, grid, wg_waves, lds, st);
     default: return hipErrorInvalidValue;
     }
 }

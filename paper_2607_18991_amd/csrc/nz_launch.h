@@ -33,8 +33,10 @@ hipError_t launch_winsum(const NzSample *desc, const NzState *state, int32_t nsa
 // residency: 0 HBM, 1 bitset in LDS, 2 bitset and parents in LDS.
 // nch in {1, 2, 4, 8, 14}.  block: 64 sites per wave step (the wave's LDS
 // slice must end with block_lds_words() words for the block's site table).
-hipError_t launch_sweep(int nch, int residency, bool block, const NzSweepArgs &a, int32_t *nstar, int32_t *mass,
-                        const int32_t *out_index, int grid, int wg_waves, hipStream_t st);
+// wide_block: some block sample has z > 512, so the block path's one-site
+// fallback needs all nch chunks (else it is compiled for at most 8).
+hipError_t launch_sweep(int nch, bool wide_block, int residency, bool block, const NzSweepArgs &a, int32_t *nstar,
+                        int32_t *mass, const int32_t *out_index, int grid, int wg_waves, hipStream_t st);
 uint32_t block_lds_words();
 
 // Periodic first-wrap sweep of a chunk whose samples all have wrap set; one
