@@ -488,16 +488,31 @@ __device__ __forceinline__ bool xcd_slot(int32_t nlist, int32_t bx, int32_t &y, 
 // table (one of each +-d pair), eight neighbour words loaded at a time.
 constexpr int HOOK_UNROLL = 8;
 
+// Summary words a hook workgroup stages in LDS (the host sizes summaries to at
+// most 1025 words).
+constexpr int32_t HOOK_SUM_MAX = 1025;
+
 __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
                                                       int32_t nlist, int32_t bx, const NzOffset *__restrict__ tabs,
                                                       uint8_t *__restrict__ ws, NzState *__restrict__ state)
 {
+    __shared__ uint32_t hsum[HOOK_SUM_MAX];
     int32_t y, x;
     if (!xcd_slot(nlist, bx, y, x)) return;
     const int sid = list[y];
     const NzSample &d = desc[sid];
     const int32_t n0 = state[sid].n0;
-    if (n0 > d.prefix_cap || d.wrap) return;
+    if (n0 > d.prefix_cap || d.wrap || x * 256 >= n0) return;   // (uniform over the workgroup)
+    // A sparse prefill (under one site in 32) leaves most bitset words empty:
+    // the workgroup stages the bitset summary in LDS and skips the loads of
+    // empty words.
+    const bool use_sum = d.sum_words > 0 && d.sum_words <= HOOK_SUM_MAX && static_cast<int64_t>(n0) * 32 < d.N;
+    if (use_sum) {
+        const uint32_t *sum_g = reinterpret_cast<const uint32_t *>(ws + d.off_sum);
+        for (int32_t w = static_cast<int32_t>(threadIdx.x); w < d.sum_words; w += 256) hsum[w] = sum_g[w];
+    }
+    __syncthreads();
+    const uint32_t gs = static_cast<uint32_t>(d.sum_shift);
     const int32_t L = d.L;
     const int32_t zh = d.z >> 1;
     const uint64_t magic = d.magic;
@@ -526,7 +541,9 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
                 const uint32_t out = o.code & ~A;
                 const bool ok = out == 0u || (periodic && (o.code & ~kCodeBits) == 0u);
                 t[q] = s + o.stride + (periodic && out ? wrap_fix(out, L) : 0);
-                w[q] = ok ? occ[static_cast<uint32_t>(t[q]) >> 5] : 0u;
+                const uint32_t wi = static_cast<uint32_t>(t[q]) >> 5;
+                const bool maybe = !use_sum || ((hsum[(wi >> gs) >> 5] >> ((wi >> gs) & 31)) & 1u);
+                w[q] = ok && maybe ? occ[wi] : 0u;
             }
 #pragma unroll
             for (int q = 0; q < HOOK_UNROLL; ++q) {
