@@ -196,6 +196,7 @@ def main():
     kernel_ms = sweep_ms_step / launches
     achieved = sl["sweep_alg_bytes"] / (sweep_ms_step / 1e3) / 1e9
     traffic = None
+    keys_traffic = None
     rec_path = os.path.join(ROOT, "profiles", "nz_sweep_L16_compact_x1000_learned.json")
     if L == 16 and S == 1000 and os.path.exists(rec_path):
         from paper_2607_18991_amd import profile_summary
@@ -203,6 +204,8 @@ def main():
         rec = json.load(open(rec_path))
         if rec.get("source_sha1") == profile_summary.source_sha1():
             traffic = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
+            if "keys" in rec:
+                keys_traffic = rec["keys"]["fetch_bytes_per_step"] + rec["keys"]["write_bytes_per_step"]
     # the keys kernel: integer VALU work of Philox4x32-10 (one block of 10
     # rounds, each two 32x32->64 products and four XORs, serves two sites) plus
     # four operations of classification per site, against 256 CUs x 64 lanes x
@@ -232,14 +235,17 @@ def main():
         "outputs_identical_plain_vs_learned": identical,
         "learned": sl,
         "plain": sp,
-        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "nz_sweep_kernel",
-                     "kernel_ms": kernel_ms, "launches_per_step": launches,
-                     "alg_bytes_per_launch": sl["sweep_alg_bytes"] / launches},
+        "roofline_sweep": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "nz_sweep_kernel",
+                           "kernel_ms": kernel_ms, "launches_per_step": launches,
+                           "alg_bytes_per_launch": sl["sweep_alg_bytes"] / launches},
         "roofline_keys": {"bound": "alu", "achieved": keys_achieved, "peak": alu_peak, "unit": "Tops/s",
-                          "frac": keys_achieved / alu_peak, "kernel": "nz_keys_kernel",
-                          "ops_per_site": keys_ops_per_site},
+                          "frac": keys_achieved / alu_peak, "traffic": keys_traffic, "kernel": "nz_keys_kernel",
+                          "kernel_ms": sl["phase_ms_per_step"]["keys_ms"], "ops_per_site": keys_ops_per_site},
     }
+    # "roofline" is the kernel that takes the larger share of the step
+    out["roofline"] = dict(out["roofline_keys"] if sl["phase_ms_per_step"]["keys_ms"] > kernel_ms * launches
+                           else out["roofline_sweep"])
     if args.l24_samples > 0:
         # the same comparison at L = 24 (7,962,624 sites): the 7 compact and 20
         # random neighbourhoods, one timed step per mode

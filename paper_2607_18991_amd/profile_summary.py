@@ -79,6 +79,7 @@ def main():
     ap.add_argument("--commands", required=True, help="text file with the three commands")
     ap.add_argument("--steps", type=int, default=2, help="bench steps in the stats run (warm-up included)")
     ap.add_argument("--sweep", default="nz::nz_sweep_kernel")
+    ap.add_argument("--keys", default="nz::nz_keys_kernel")
     ap.add_argument("--outdir", default=os.path.join(HERE, "..", "profiles"))
     args = ap.parse_args()
 
@@ -106,6 +107,11 @@ def main():
     launches = max(1, sum(v[0] for k, v in fetch.items() if k.startswith(args.sweep)))
     rec = {"kernel": args.sweep, "launches": launches, "fetch_bytes_per_launch": sweep_f / launches,
            "write_bytes_per_launch": sweep_w / launches, "source_sha1": source_sha1()}
+    # the keys kernel (the counter runs time one step): bytes over the step's launches
+    keys_f = sum(v[1] for k, v in fetch.items() if k.startswith(args.keys)) * 1024 * FETCH_SCALE
+    keys_w = sum(v[1] for k, v in write.items() if k.startswith(args.keys)) * 1024 * WRITE_SCALE
+    rec["keys"] = {"kernel": args.keys, "fetch_bytes_per_step": keys_f, "write_bytes_per_step": keys_w,
+                   "dispatches": sum(v[0] for k, v in fetch.items() if k.startswith(args.keys))}
     lines += ["", f"Sweep kernel per launch: {rec['fetch_bytes_per_launch'] / 1e9:.3f} GB fetched, "
                   f"{rec['write_bytes_per_launch'] / 1e9:.3f} GB written over {launches} launches; kernel source "
                   f"SHA-1 {rec['source_sha1'][:12]}.", ""]
