@@ -241,10 +241,13 @@ def main():
                            "alg_bytes_per_launch": sl["sweep_alg_bytes"] / launches},
         "roofline_keys": {"bound": "alu", "achieved": keys_achieved, "peak": alu_peak, "unit": "Tops/s",
                           "frac": keys_achieved / alu_peak, "traffic": keys_traffic, "kernel": "nz_keys_kernel",
-                          "kernel_ms": sl["phase_ms_per_step"]["keys_ms"], "ops_per_site": keys_ops_per_site},
+                          "kernel_ms": sl["phase_ms_per_step"]["keys_ms"] / launches, "launches_per_step": launches,
+                          "ops_per_site": keys_ops_per_site},
     }
-    # "roofline" is the kernel that takes the larger share of the step
-    out["roofline"] = dict(out["roofline_keys"] if sl["phase_ms_per_step"]["keys_ms"] > kernel_ms * launches
+    # "roofline" is the kernel that takes the larger share of the step (a batch
+    # whose narrow and wide neighbourhoods run side by side has one launch of
+    # each kernel per group; rates are per launch over its own duration)
+    out["roofline"] = dict(out["roofline_keys"] if sl["phase_ms_per_step"]["keys_ms"] > sweep_ms_step
                            else out["roofline_sweep"])
     if args.l24_samples > 0:
         # the same comparison at L = 24 (7,962,624 sites): the 7 compact and 20

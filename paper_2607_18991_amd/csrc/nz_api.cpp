@@ -12,7 +12,9 @@
 #include <cstdio>
 #include <cstring>
 #include <map>
+#include <mutex>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "../../include/nz.h"
@@ -143,11 +145,16 @@ int device_info(Device &dev)
 {
     int id = 0;
     HIP_TRY(hipGetDevice(&id));
-    static thread_local std::map<int, Device> cache;
-    auto it = cache.find(id);
-    if (it != cache.end()) {
-        dev = it->second;
-        return NZ_OK;
+    // one cache for the process (the two-group path queries from a second thread)
+    static std::mutex lock;
+    static std::map<int, Device> cache;
+    {
+        std::lock_guard<std::mutex> g(lock);
+        auto it = cache.find(id);
+        if (it != cache.end()) {
+            dev = it->second;
+            return NZ_OK;
+        }
     }
     hipDeviceProp_t p;
     HIP_TRY(hipGetDeviceProperties(&p, id));
@@ -158,6 +165,7 @@ int device_info(Device &dev)
     int optin = 0;
     if (hipDeviceGetAttribute(&optin, hipDeviceAttributeSharedMemPerBlockOptin, id) == hipSuccess && optin > 0)
         dev.lds_per_block = std::max(dev.lds_per_block, static_cast<size_t>(optin));
+    std::lock_guard<std::mutex> g(lock);
     cache[id] = dev;
     return NZ_OK;
 }
@@ -401,8 +409,11 @@ struct SmaxReq {
     uint64_t *d_out;
 };
 
+// job_out (may be NULL): first output index of every job (default: the
+// samples of the jobs in order, from 0).
 int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_t *d_nstar, int32_t *d_mass,
-              int32_t *h_backoffs, const Tune &tune, hipStream_t st, const SmaxReq *smax = nullptr)
+              int32_t *h_backoffs, const Tune &tune, hipStream_t st, const SmaxReq *smax = nullptr,
+              const int64_t *job_out = nullptr)
 {
     Device dev;
     if (int rc = device_info(dev)) return rc;
@@ -424,7 +435,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             Plan p{};
             p.job = j;
             p.sample = J.sample0 + k;
-            p.out = static_cast<int32_t>(out++);
+            p.out = static_cast<int32_t>(job_out ? job_out[j] + k : out);
+            ++out;
             p.L = J.L;
             p.mask = J.zone_mask;
             p.n0 = J.n0 > 0 ? J.n0 : 0;
@@ -440,7 +452,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             todo.push_back(p);
         }
     }
-    if (out > 0x7FFFFFFF) return fail(NZ_EINVAL, "too many samples in one batch");
+    if (out > 0x7FFFFFFF || (job_out && njobs > 0 && job_out[njobs - 1] + jobs[njobs - 1].nsamples > 0x7FFFFFFF))
+        return fail(NZ_EINVAL, "too many samples in one batch");
     const size_t tab_bytes = align_up(pool.entries.size() * sizeof(NzOffset));
 
     int rounds = 0;
@@ -568,10 +581,9 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
 
             // ---- launches
             PhaseEvents *pe = nullptr;
-            static thread_local PhaseEvents *events = nullptr;
             if (g_timing) {
-                if (!events) events = new PhaseEvents();
-                if (events->ok) pe = events;
+                static thread_local PhaseEvents events;   // released when the thread ends
+                if (events.ok) pe = &events;
             }
             if (pe) HIP_TRY(hipEventRecord(pe->ev[0], st));
             HIP_TRY(nz::launch_clear(d_desc, nullptr, n, ws, d_state, st));
@@ -840,6 +852,119 @@ NZ_API int nz_last_batch_timing(double ms[6])
     return NZ_OK;
 }
 
+// ---------------------------------------------------------------------------
+// Two groups at once.  Narrow neighbourhoods (z <= 64) spend their sweep in
+// long chains of dependent 64-site steps that keep few waves busy; a batch that
+// also holds wider ones runs the two groups side by side (the wide group on a
+// second host thread and stream), so that one group's sweep overlaps the
+// other's keys and labelling.  Each group gets its own share of the workspace.
+
+constexpr int64_t kSplitMinSamples = 512;
+
+struct SplitPlan {
+    std::vector<nz_job> job[2];
+    std::vector<int32_t> index[2];   // caller's job index of every job of a group
+    std::vector<int64_t> out[2];     // first output index of every job of a group
+    size_t bytes[2] = {0, 0};
+};
+
+bool split_groups(const nz_job *jobs, int32_t njobs, const Tune &tune, SplitPlan &sp)
+{
+    if (getenv("NZ_DEBUG_NO_SPLIT")) return false;
+    int64_t o = 0, count[2] = {0, 0};
+    for (int j = 0; j < njobs; ++j) {
+        const int g = coordination(jobs[j].zone_mask) <= 64 ? 0 : 1;
+        if (jobs[j].nsamples > 0) {
+            sp.job[g].push_back(jobs[j]);
+            sp.index[g].push_back(j);
+            sp.out[g].push_back(o);
+            count[g] += jobs[j].nsamples;
+        }
+        o += jobs[j].nsamples;
+    }
+    if (count[0] < kSplitMinSamples || count[1] < kSplitMinSamples) return false;
+    for (int g = 0; g < 2; ++g) sp.bytes[g] = batch_bytes(sp.job[g].data(), static_cast<int32_t>(sp.job[g].size()), tune);
+    return true;
+}
+
+// The second group's stream, its start event and host thread live per host
+// thread and device.
+struct SideStream {
+    hipStream_t st = nullptr;
+    hipEvent_t start = nullptr;
+    bool ok = false;
+};
+
+SideStream *side_stream(int device)
+{
+    static thread_local std::map<int, SideStream> per_device;
+    SideStream &s = per_device[device];
+    if (!s.ok && !s.st)
+        s.ok = hipStreamCreateWithFlags(&s.st, hipStreamNonBlocking) == hipSuccess &&
+               hipEventCreateWithFlags(&s.start, hipEventDisableTiming) == hipSuccess;
+    return s.ok ? &s : nullptr;
+}
+
+int run_split(SplitPlan &sp, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_t *d_nstar, int32_t *d_mass,
+              int32_t *h_backoffs, const Tune &tune, hipStream_t st)
+{
+    int device = 0;
+    HIP_TRY(hipGetDevice(&device));
+    SideStream *side = side_stream(device);
+    if (!side) return fail(NZ_EDEVICE, "could not create the second stream");
+    // workspace shares in proportion to the groups' resident sizes
+    const size_t wa = static_cast<size_t>(static_cast<long double>(ws_bytes) * sp.bytes[0] /
+                                          (sp.bytes[0] + sp.bytes[1])) / kAlign * kAlign;
+    std::vector<int32_t> back[2];
+    for (int g = 0; g < 2; ++g) back[g].assign(sp.job[g].size(), 0);
+    // the second group starts after the work already queued on the caller's stream
+    HIP_TRY(hipEventRecord(side->start, st));
+    HIP_TRY(hipStreamWaitEvent(side->st, side->start, 0));
+    int rc_b = NZ_OK;
+    std::string err_b;
+    int64_t stats_b[6] = {0, 0, 0, 0, 0, 0};
+    double ms_b[6] = {0, 0, 0, 0, 0, 0};
+    const bool timing = g_timing;
+    std::thread worker([&]() {
+        try {
+            if (hipSetDevice(device) != hipSuccess) {
+                rc_b = fail(NZ_EDEVICE, "hipSetDevice failed on the second thread");
+            } else {
+                g_timing = timing;
+                rc_b = run_batch(sp.job[1].data(), static_cast<int32_t>(sp.job[1].size()), ws + wa, ws_bytes - wa,
+                                 d_nstar, d_mass, back[1].data(), tune, side->st, nullptr, sp.out[1].data());
+            }
+        } catch (...) {
+            rc_b = fail(NZ_ENOMEM, "host allocation failed");
+        }
+        if (rc_b != NZ_OK) err_b = g_err;
+        for (int k = 0; k < 6; ++k) {
+            stats_b[k] = g_stats[k];
+            ms_b[k] = g_ms[k];
+        }
+    });
+    int rc_a;
+    try {
+        rc_a = run_batch(sp.job[0].data(), static_cast<int32_t>(sp.job[0].size()), ws, wa, d_nstar, d_mass,
+                         back[0].data(), tune, st, nullptr, sp.out[0].data());
+    } catch (...) {
+        rc_a = fail(NZ_ENOMEM, "host allocation failed");
+    }
+    worker.join();
+    for (int k = 0; k < 6; ++k) {
+        g_stats[k] += stats_b[k];
+        g_ms[k] += ms_b[k];
+    }
+    if (rc_a != NZ_OK) return rc_a;
+    if (rc_b != NZ_OK) return fail(rc_b, "%s", err_b.c_str());
+    if (h_backoffs) {
+        for (int j = 0; j < njobs; ++j) h_backoffs[j] = 0;
+        for (int g = 0; g < 2; ++g)
+            for (size_t k = 0; k < sp.job[g].size(); ++k) h_backoffs[sp.index[g][k]] = back[g][k];
+    }
+    return NZ_OK;
+}
+
 NZ_API int nz_batch_workspace_bytes(const nz_job *jobs, int32_t njobs, const nz_tuning *tune, size_t *bytes)
 {
     if (!bytes) return fail(NZ_EINVAL, "bytes is NULL");
@@ -849,7 +974,8 @@ NZ_API int nz_batch_workspace_bytes(const nz_job *jobs, int32_t njobs, const nz_
     Tune t;
     if (int rc = read_tune(tune, t)) return rc;
     try {
-        *bytes = batch_bytes(jobs, njobs, t);
+        SplitPlan sp;
+        *bytes = split_groups(jobs, njobs, t, sp) ? sp.bytes[0] + sp.bytes[1] + kAlign : batch_bytes(jobs, njobs, t);
     } catch (...) {
         return fail(NZ_ENOMEM, "host allocation failed while sizing the workspace");
     }
@@ -879,8 +1005,14 @@ NZ_API int nz_sweep_batch(const nz_job *jobs, int32_t njobs, void *d_ws, size_t 
     }
     int rc;
     try {
-        rc = run_batch(jobs, njobs, static_cast<uint8_t *>(d_ws), ws_bytes, d_nstar, d_mass, h_backoffs, t,
-                       static_cast<hipStream_t>(stream));
+        // two groups side by side when the workspace holds both resident
+        SplitPlan sp;
+        if (split_groups(jobs, njobs, t, sp) && ws_bytes >= sp.bytes[0] + sp.bytes[1] + kAlign)
+            rc = run_split(sp, njobs, static_cast<uint8_t *>(d_ws), ws_bytes, d_nstar, d_mass, h_backoffs, t,
+                           static_cast<hipStream_t>(stream));
+        else
+            rc = run_batch(jobs, njobs, static_cast<uint8_t *>(d_ws), ws_bytes, d_nstar, d_mass, h_backoffs, t,
+                           static_cast<hipStream_t>(stream));
     } catch (...) {
         rc = fail(NZ_ENOMEM, "host allocation failed");
     }

@@ -121,3 +121,17 @@ def test_boundary_codes():
     with pytest.raises(nz.NzError) as e:
         nz.nz_smax_window(4, 1, 1, 0, 2, 10, 20, boundary=nz.NZ_PERIODIC)
     assert e.value.code == nz.NZ_EUNSUPPORTED
+
+
+def test_workspace_covers_two_groups(monkeypatch):
+    """A batch with enough narrow (z <= 64) and wide samples runs as two groups,
+    each with its own resident share of the workspace."""
+    jobs = [dict(L=16, zone_mask=m, seed=1, nsamples=1000, n0=-1) for m in (0x01, 0x03, 0x07, 0x7F)]
+    both = nz.nz_batch_workspace_bytes(jobs)
+    monkeypatch.setenv("NZ_DEBUG_NO_SPLIT", "1")
+    one = nz.nz_batch_workspace_bytes(jobs)
+    assert both > one
+    # too few wide samples: one group
+    small = jobs[:3] + [dict(jobs[3], nsamples=100)]
+    monkeypatch.delenv("NZ_DEBUG_NO_SPLIT")
+    assert nz.nz_batch_workspace_bytes(small) < nz.nz_batch_workspace_bytes(jobs)
