@@ -38,9 +38,16 @@ constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
 constexpr uint32_t kWeylA = 0x9E3779B9u;
 constexpr uint32_t kWeylB = 0xBB67AE85u;
 
+// Three-input XOR in one gfx950 instruction (v_bitop3_b32, truth table 0x96).
+__device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
+{
+    return __builtin_amdgcn_bitop3_b32(a, b, c, 0x96);
+}
+
 // Keys of sites 2j and 2j + 1: both come from the block of counter j (word 3:
 // domain tag 0); the even site takes words (1, 0), the odd site words (3, 2).
-// Each round's two 32x32 products are formed as full 64-bit products.
+// Each round's two 32x32 products are formed as full 64-bit products (one
+// v_mad_u64_u32 each) and each of its two three-way XORs is one instruction.
 __device__ __forceinline__ void site_key_pair(uint32_t seed_lo, uint32_t seed_hi, uint32_t smp_lo, uint32_t smp_hi,
                                               uint32_t j, uint64_t &k_even, uint64_t &k_odd)
 {
@@ -50,9 +57,9 @@ __device__ __forceinline__ void site_key_pair(uint32_t seed_lo, uint32_t seed_hi
     for (int r = 0; r < 10; ++r) {
         const uint64_t a = static_cast<uint64_t>(kPhiloxMulA) * c0;
         const uint64_t b = static_cast<uint64_t>(kPhiloxMulB) * c2;
-        c0 = static_cast<uint32_t>(b >> 32) ^ c1 ^ k0;
+        c0 = xor3(static_cast<uint32_t>(b >> 32), c1, k0);
         c1 = static_cast<uint32_t>(b);
-        c2 = static_cast<uint32_t>(a >> 32) ^ c3 ^ k1;
+        c2 = xor3(static_cast<uint32_t>(a >> 32), c3, k1);
         c3 = static_cast<uint32_t>(a);
         k0 += kWeylA;
         k1 += kWeylB;
