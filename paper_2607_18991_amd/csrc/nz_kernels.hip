@@ -1407,25 +1407,39 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
             int32_t fstride[FB];
             uint32_t fcode[FB];
             bool done = false;
-            // Block cursor over the band: bucket cb, offset cj of the next block.
-            // A block's sites are loaded one block ahead, so that load overlaps
-            // the previous block's step.  1: pc holds the block's sites (lanes
-            // < n); 0: end of the band; -1: an over-full bucket was reached.
+            // Block cursor over the band: bucket cb, offset cj of the next site.
+            // The concatenated buckets are the order, so a block takes the next
+            // 64 sites across bucket boundaries.  Its sites are loaded one block
+            // ahead, so that load overlaps the previous block's step.  1: pc
+            // holds the block's sites (lanes < n); 0: end of the band; -1: an
+            // over-full bucket was reached (the sites before it still form a
+            // block first).
             int32_t cb = 0;
             uint32_t cj = 0;
             uint32_t ccnt = nb > 0 ? counts[0] : 0u;
             auto next_block = [&](uint32_t &pc, int &n) -> int {
-                while (cb < nb && cj >= ccnt) {
-                    ++cb;
-                    cj = 0;
-                    if (cb < nb) ccnt = counts[cb];
+                n = 0;
+                pc = 0u;
+                bool over = false;
+                while (n < 64) {
+                    while (cb < nb && cj >= ccnt) {
+                        ++cb;
+                        cj = 0;
+                        if (cb < nb) ccnt = counts[cb];
+                    }
+                    if (cb >= nb) break;
+                    if (ccnt > cap) {
+                        over = true;
+                        break;
+                    }
+                    const uint32_t t = min(static_cast<uint32_t>(64 - n), ccnt - cj);
+                    const uint32_t rel = lane - static_cast<uint32_t>(n);   // this lane's entry, if in range
+                    if (lane >= static_cast<uint32_t>(n) && rel < t) pc = sites[static_cast<uint64_t>(cb) * cap + cj + rel];
+                    n += static_cast<int>(t);
+                    cj += t;
                 }
-                if (cb >= nb) return 0;
-                if (ccnt > cap) return -1;
-                n = static_cast<int>(min(64u, ccnt - cj));
-                pc = static_cast<int>(lane) < n ? sites[static_cast<uint64_t>(cb) * cap + cj + lane] : 0u;
-                cj += 64u;
-                return 1;
+                if (n > 0) return 1;
+                return over ? -1 : 0;
             };
             uint32_t pcl = 0;
             int nbk = 0;
