@@ -160,7 +160,7 @@ typedef struct {
  *                   2: everything in HBM; 3: bitset and parents in LDS.
  *   wg_waves        waves per workgroup of the sweep (1..4).
  *   waves_per_simd  resident sweep waves per SIMD of the persistent launch.
- *   bucket_log2     log2 of the mean number of keys per sort bucket (4..10).
+ *   bucket_log2     log2 of the mean number of keys per sort bucket (4..10; 0: 7).
  *   sweep_mode      1: one site per wave step (z lanes check the neighbours);
  *                   2: 64 sites per wave step (one site per lane; the block's
  *                   unions are merged by a connected-components pass in LDS;

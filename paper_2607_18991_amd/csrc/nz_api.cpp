@@ -310,7 +310,7 @@ struct Tune {
     int residency = 0;
     int wg_waves = 0;
     int waves_per_simd = 0;
-    int bucket_log2 = 8;
+    int bucket_log2 = 7;   // mean keys per sort bucket: 128 (256 measured slower at L = 16, 64 no faster)
     int dcap = 64;
     int sweep_mode = 0;
 };
