@@ -38,6 +38,17 @@ constexpr uint32_t kPhiloxMulB = 0xCD9E8D57u;
 constexpr uint32_t kWeylA = 0x9E3779B9u;
 constexpr uint32_t kWeylB = 0xBB67AE85u;
 
+// 32x32 -> 64-bit product as one v_mad_u64_u32 (left to itself the compiler
+// forms the last round's products with separate v_mul_hi_u32 / v_mul_lo_u32,
+// two more quarter-rate instructions per Philox block).
+__device__ __forceinline__ uint64_t mul_wide(uint32_t x, uint32_t m)
+{
+    uint64_t r, carry;
+    asm("v_mad_u64_u32 %0, %1, %2, %3, 0" : "=v"(r), "=&s"(carry) : "v"(x), "s"(m));
+    (void)carry;
+    return r;
+}
+
 // Three-input XOR in one gfx950 instruction (v_bitop3_b32, truth table 0x96).
 __device__ __forceinline__ uint32_t xor3(uint32_t a, uint32_t b, uint32_t c)
 {
@@ -55,8 +66,9 @@ __device__ __forceinline__ void site_key_pair(uint32_t seed_lo, uint32_t seed_hi
     uint32_t k0 = seed_lo, k1 = seed_hi;
 #pragma unroll
     for (int r = 0; r < 10; ++r) {
-        const uint64_t a = static_cast<uint64_t>(kPhiloxMulA) * c0;
-        const uint64_t b = static_cast<uint64_t>(kPhiloxMulB) * c2;
+        const uint64_t a = mul_wide(c0, kPhiloxMulA);
+        // round 0's c2 is the sample's high word, the same in every lane
+        const uint64_t b = r == 0 ? static_cast<uint64_t>(kPhiloxMulB) * c2 : mul_wide(c2, kPhiloxMulB);
         c0 = xor3(static_cast<uint32_t>(b >> 32), c1, k0);
         c1 = static_cast<uint32_t>(b);
         c2 = xor3(static_cast<uint32_t>(a >> 32), c3, k1);
