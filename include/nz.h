@@ -168,6 +168,11 @@ typedef struct {
  *                   that does not fit the LDS tables, is redone one site at a
  *                   time); 0: 64 sites per step for z <= 512, one site per
  *                   step for wider neighbourhoods.
+ *   summary         the HBM-resident sweep reads, before each occupancy load,
+ *                   a one-bit-per-block summary of the bitset held in LDS and
+ *                   skips loads of all-empty words.  1: on; 2: off; 0: on when
+ *                   the chunk has at least 2 samples per compute unit (with
+ *                   fewer resident waves the extra LDS read is not repaid).
  */
 typedef struct {
     int32_t residency;
@@ -175,6 +180,7 @@ typedef struct {
     int32_t waves_per_simd;
     int32_t bucket_log2;
     int32_t sweep_mode;
+    int32_t summary;
 } nz_tuning;
 
 /* Device workspace bytes that lets nz_sweep_batch run the jobs with all their

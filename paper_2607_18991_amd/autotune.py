@@ -1,8 +1,9 @@
 """Autotuner of the persistent sweep: for every (L, z-class) it times the
 candidate launch shapes on the GPU -- where the per-sample state lives (HBM,
 occupancy bitset in LDS, bitset and parents in LDS), waves per workgroup,
-resident waves per SIMD, and one site or 64 sites per wave step -- and keeps
-the fastest in a JSON table shipped with the package.  Tuning never changes an
+resident waves per SIMD, one site or 64 sites per wave step, and whether the
+HBM-resident sweep checks the bitset summary -- and keeps the fastest in a
+JSON table shipped with the package.  Tuning never changes an
 output (the library guarantees it and the tests check it); it only moves time.
 
 z-classes follow the offset chunks the kernels are compiled for: z <= 64, 128,
@@ -50,7 +51,8 @@ def candidates(L: int):
     for mode in (1, 2):
         for wps in (4, 8):
             for wg in (1, 4):
-                out.append(dict(residency=2, wg_waves=wg, waves_per_simd=wps, sweep_mode=mode))
+                for summary in (1, 2):
+                    out.append(dict(residency=2, wg_waves=wg, waves_per_simd=wps, sweep_mode=mode, summary=summary))
         if bitset_bytes <= 150 * 1024:
             out.append(dict(residency=1, wg_waves=1, waves_per_simd=8, sweep_mode=mode))
         if bitset_bytes + 4 * N <= 150 * 1024:
@@ -130,8 +132,8 @@ def signature(jobs) -> str:
 
 
 def batch_candidates():
-    return [dict(residency=2, wg_waves=wg, waves_per_simd=wps, sweep_mode=mode)
-            for mode in (0, 1, 2) for wps in (4, 8) for wg in (1, 4)]
+    return [dict(residency=2, wg_waves=wg, waves_per_simd=wps, sweep_mode=mode, summary=summary)
+            for mode in (0, 1, 2) for wps in (4, 8) for wg in (1, 4) for summary in (1, 2)]
 
 
 def tune_batch(jobs, reps: int = 2, log=None):
@@ -176,12 +178,19 @@ def load_table(path: str = TABLE_PATH):
     return _table
 
 
-def lookup(L: int, zone_mask: int, table=None):
+def lookup(L: int, zone_mask: int, table=None, nsamples: int | None = None):
     """Tuning dict for one (L, neighbourhood); {} (library defaults) if the
-    table has no entry for it."""
+    table has no entry for it.  The summary choice depends on how many samples
+    share the chip, so it is kept only for batches of at most as many samples
+    as the entry was timed on (larger ones get the library's choice)."""
     t = table or load_table()
     e = t["entries"].get(key(L, zclass(nz.nz_coordination(zone_mask))))
-    return dict(e["tune"]) if e else {}
+    if not e:
+        return {}
+    tune = dict(e["tune"])
+    if nsamples is not None and nsamples > int(e.get("samples", 0)):
+        tune.pop("summary", None)
+    return tune
 
 
 # an LDS-resident sample takes a whole CU's LDS, so such residencies pay only
@@ -202,8 +211,8 @@ def for_jobs(jobs, table=None):
     if e:
         return dict(e["tune"])
     j = max(jobs, key=lambda j: (int(j["L"]), -nz.nz_coordination(int(j["zone_mask"]))))
-    tune = lookup(int(j["L"]), int(j["zone_mask"]), t)
     total = sum(int(j["nsamples"]) for j in jobs)
+    tune = lookup(int(j["L"]), int(j["zone_mask"]), t, total)
     if tune.get("residency") in (1, 3) and total > LDS_RESIDENT_MAX_SAMPLES:
         tune.update(residency=2, wg_waves=1)
     return tune

@@ -184,6 +184,11 @@ double pc_prior(int z) { return 1.553 / (z + 1.01); }
 
 // 32-bit words of a sample's bitset summary in the sweep's LDS slice
 constexpr int64_t kSumWords = 1024;
+// The sweep consults the summary (automatic choice) when its chunk has at least
+// this many samples per CU: measured at L = 16..24, the skipped loads pay once
+// several waves share a CU, while at about one wave per CU the extra LDS read
+// before each load costs 5-20% of the sweep.
+constexpr int32_t kSumSamplesPerCu = 2;
 
 struct Plan {
     int32_t job;
@@ -199,6 +204,7 @@ struct Plan {
     double prio;
     int64_t win_lo, win_hi;   // smax mode: S_max(n) for n in [win_lo, win_hi) (win_hi = 0: off)
     bool wrap;           // periodic first-wrap sample (64-bit union-find entries)
+    bool per;            // periodic coordinates (first-wrap or largest-cluster windows)
 };
 
 uint64_t rank_to_key(int64_t n, int64_t N)
@@ -313,6 +319,7 @@ struct Tune {
     int bucket_log2 = 7;   // mean keys per sort bucket: 128 (256 measured slower at L = 16, 64 no faster)
     int dcap = 64;
     int sweep_mode = 0;
+    int summary = 0;
 };
 
 int check_job(const nz_job &j, int idx)
@@ -344,6 +351,8 @@ int read_tune(const nz_tuning *t, Tune &out)
         return fail(NZ_EINVAL, "tuning: bucket_log2 %d outside [4, 10]", t->bucket_log2);
     if (t->sweep_mode < 0 || t->sweep_mode > 2) return fail(NZ_EINVAL, "tuning: sweep_mode %d outside [0, 2]", t->sweep_mode);
     out.sweep_mode = t->sweep_mode;
+    if (t->summary < 0 || t->summary > 2) return fail(NZ_EINVAL, "tuning: summary %d outside [0, 2]", t->summary);
+    out.summary = t->summary;
     out.residency = t->residency;
     out.wg_waves = t->wg_waves;
     out.waves_per_simd = t->waves_per_simd;
@@ -448,7 +457,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             p.prio = J.prio > 0 ? J.prio : static_cast<double>(std::max<int64_t>(1, p.band_hi - p.n0)) * (1.0 + z / 64.0);
             p.win_lo = smax ? smax->win_lo : 0;
             p.win_hi = smax ? smax->win_hi : 0;
-            p.wrap = J.boundary == NZ_PERIODIC && !smax;
+            p.per = J.boundary == NZ_PERIODIC;
+            p.wrap = p.per && !smax;
             todo.push_back(p);
         }
     }
@@ -459,10 +469,10 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
     int rounds = 0;
     while (!todo.empty()) {
         if (++rounds > 64) return fail(NZ_EDEVICE, "samples still unfinished after 64 redo rounds");
-        // free-boundary samples first, then the periodic first-wrap ones: a chunk
-        // holds one kind only, since the two use different kernels
+        // free-boundary samples first, then the periodic ones: a chunk holds one
+        // boundary condition only, since the sweep is compiled for each
         std::stable_sort(todo.begin(), todo.end(), [](const Plan &a, const Plan &b) {
-            return a.wrap != b.wrap ? b.wrap : a.prio > b.prio;
+            return a.per != b.per ? b.per : a.prio > b.prio;
         });
         std::vector<Plan> redo;
         size_t pos = 0;
@@ -475,7 +485,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             std::vector<Sizes> sizes;
             size_t used = head;
             while (pos < todo.size() && static_cast<int32_t>(chunk.size()) < cmax) {
-                if (!chunk.empty() && todo[pos].wrap != chunk.front().wrap) break;
+                if (!chunk.empty() && todo[pos].per != chunk.front().per) break;
                 Sizes s = plan_sizes(todo[pos], tune.bucket_log2);
                 if (used + s.total > ws_bytes) break;
                 used += s.total;
@@ -490,6 +500,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             ++g_stats[0];
             const int32_t n = static_cast<int32_t>(chunk.size());
             const bool wrap_chunk = chunk.front().wrap;
+            const bool per_chunk = chunk.front().per;
 
             // ---- descriptors, grouped by L for the keys launches
             std::vector<int32_t> byL(n);
@@ -500,6 +511,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             std::vector<int32_t> chunk_of_desc(n);
             size_t off = head;
             int32_t max_nb = 0, max_cap = 0, max_z = 0, max_sum = 0;
+            const bool use_sum = tune.summary == 1 || (tune.summary == 0 && n >= kSumSamplesPerCu * dev.cus);
             uint32_t max_N = 0;
             int64_t max_site = 0;
             std::vector<int32_t> desc_of_chunk(n);
@@ -545,7 +557,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 max_nb = std::max(max_nb, d.nb);
                 max_cap = std::max(max_cap, d.cap);
                 max_z = std::max(max_z, d.z);
-                max_sum = std::max(max_sum, d.sum_words);
+                if (use_sum) max_sum = std::max(max_sum, d.sum_words);
                 max_N = std::max(max_N, static_cast<uint32_t>(d.N));
                 if (d.T0 != 0) {
                     prefill_list.push_back(di);
@@ -667,7 +679,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 int32_t min_z = 1 << 30;
                 for (const NzSample &d : desc) min_z = std::min(min_z, d.z);
                 const int32_t blk_zmax = tune.sweep_mode == 2 ? 892 : 512;
-                const bool block = tune.sweep_mode == 2 || (tune.sweep_mode == 0 && min_z <= blk_zmax);
+                // periodic (largest-cluster) samples go one site per step
+                const bool block = !per_chunk && (tune.sweep_mode == 2 || (tune.sweep_mode == 0 && min_z <= blk_zmax));
                 if (block) lds_words += nz::block_lds_words();
                 int wg_waves = tune.wg_waves ? tune.wg_waves : (residency ? 1 : 4);
                 int wps = tune.waves_per_simd ? tune.waves_per_simd : 8;
@@ -691,12 +704,13 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 args.dcap = tune.dcap;
                 args.blk_old = env_blk_old();
                 args.blk_zmax = blk_zmax;
+                args.use_sum = use_sum ? 1 : 0;
                 // the block path's fallback needs more than 8 offset chunks only
                 // when a sample wider than z = 512 goes 64 sites per step
                 bool wide_block = false;
                 for (const NzSample &d : desc) wide_block = wide_block || (block && d.z > 512 && d.z <= blk_zmax && !d.smax_mode);
-                HIP_TRY(nz::launch_sweep(nch_for(max_z), wide_block, residency, block, args, d_nstar, d_mass, d_outidx, grid,
-                                         wg_waves, st));
+                HIP_TRY(nz::launch_sweep(nch_for(max_z), wide_block, residency, block, per_chunk, args, d_nstar, d_mass,
+                                         d_outidx, grid, wg_waves, st));
             }
             if (smax)
                 HIP_TRY(nz::launch_winsum(d_desc, d_state, n, static_cast<int32_t>(smax->win_hi - smax->win_lo), ws,

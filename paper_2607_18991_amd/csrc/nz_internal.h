@@ -92,4 +92,5 @@ struct NzSweepArgs {
     int32_t dcap;             // distinct roots held per step before an early merge (2..64)
     int32_t blk_old;          // block sweep: earlier roots one block may touch (0..256)
     int32_t blk_zmax;         // block sweep for samples with z <= blk_zmax, one site per step above
+    int32_t use_sum;          // 1: HBM-resident samples check the bitset summary before occupancy loads
 };

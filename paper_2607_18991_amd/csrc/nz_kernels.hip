@@ -915,14 +915,15 @@ struct BandCursor {
 };
 
 // One sequential step's site and the occupancy words of its neighbours (lane
-// c*64 + lane holds neighbour c of the offset table).
-template <int NCH>
+// c*64 + lane holds neighbour c of the offset table).  PER: coordinates wrap
+// modulo L (periodic boundaries); a compile-time choice, so that the
+// free-boundary step carries no wrap arithmetic.
+template <int NCH, bool PER = false>
 struct SiteStep {
     int32_t s;
     uint32_t fl;
     uint32_t own;
     uint32_t A;          // allowed axes of s
-    bool per;            // periodic boundaries
     uint32_t word[NCH];  // 0 for a neighbour outside the lattice
 
     // Neighbour c of s (recomputed rather than held: one register per chunk
@@ -930,26 +931,30 @@ struct SiteStep {
     __device__ __forceinline__ int32_t nbr(int c, const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH],
                                            int32_t L) const
     {
-        const uint32_t out = ocode[c] & ~A;
-        return s + ostride[c] + (per && out ? wrap_fix(out, L) : 0);
+        if constexpr (PER) {
+            const uint32_t out = ocode[c] & ~A;
+            return s + ostride[c] + (out ? wrap_fix(out, L) : 0);
+        } else {
+            return s + ostride[c];
+        }
     }
-    // neighbour c lies inside the lattice (or wraps, under periodic boundaries)
+    // neighbour c lies inside the lattice (under periodic boundaries every
+    // offset does, padding slots aside)
     __device__ __forceinline__ bool inside(int c, const uint32_t (&ocode)[NCH]) const
     {
-        return (ocode[c] & ~A) == 0u || (per && (ocode[c] & ~kCodeBits) == 0u);
+        if constexpr (PER) return (ocode[c] & ~kCodeBits) == 0u;
+        else return (ocode[c] & ~A) == 0u;
     }
 
     template <int RES>
     __device__ __forceinline__ void prepare(const SweepMem<RES> &m, uint32_t *lds, uint32_t pc, int32_t L,
-                                            const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH],
-                                            bool periodic = false)
+                                            const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH])
     {
         const int32_t x0 = pc & 63, x1 = (pc >> 6) & 63, x2 = (pc >> 12) & 63, x3 = (pc >> 18) & 63, x4 = pc >> 24;
         s = x0 + L * (x1 + L * (x2 + L * (x3 + L * x4)));
         A = allowed_axis(x0, L) | (allowed_axis(x1, L) << 5) | (allowed_axis(x2, L) << 10) |
             (allowed_axis(x3, L) << 15) | (allowed_axis(x4, L) << 20);
-        per = periodic;
-        fl = periodic ? 0u : ((x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u));
+        fl = PER ? 0u : ((x0 == 0 ? NZ_FLO : 0u) | (x0 == L - 1 ? NZ_FHI : 0u));
         own = m.occ_ld(lds, static_cast<uint32_t>(s) >> 5);
 #pragma unroll
         for (int c = 0; c < NCH; ++c)
@@ -977,8 +982,8 @@ constexpr bool kLookahead = NCH <= 2;
 // roots of its occupied neighbours (lanes 0..D-1 hold them, entry 0 being the
 // site itself), and merge them into the largest.  Returns the merged cluster's
 // size and border flags.
-template <int NCH, int RES>
-__device__ __forceinline__ void sweep_step(const SweepMem<RES> &m, uint32_t *lds, const SiteStep<NCH> &cur,
+template <int NCH, int RES, bool PER>
+__device__ __forceinline__ void sweep_step(const SweepMem<RES> &m, uint32_t *lds, const SiteStep<NCH, PER> &cur,
                                            const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH], int32_t L,
                                            int dcap, uint32_t &total, uint32_t &flags)
 {
@@ -1294,9 +1299,10 @@ struct SweepOut {
 // sweep's one-site fallback (z <= 64 * FB for every block sample), kept
 // separate so that a launch whose wide neighbourhoods go one site at a time
 // does not carry their registers through the block path.
-template <int NCH, int RES, bool BLOCK, int FB>
+template <int NCH, int RES, bool BLOCK, int FB, bool PER>
 __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut out)
 {
+    static_assert(!(BLOCK && PER), "periodic samples go one site per step");
     extern __shared__ uint32_t lds[];
     __shared__ int32_t claim[16];   // per-wave work claim
     const uint32_t lane = lane_id();
@@ -1331,10 +1337,12 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         m.sshift = static_cast<uint32_t>(d.sum_shift);
         m.sum_on = false;
         if constexpr (RES == RES_HBM) {
-            m.sum_on = d.sum_words > 0;
-            const uint32_t *sum_g = reinterpret_cast<const uint32_t *>(a.ws + d.off_sum);
-            for (int32_t w = lane; w < d.sum_words; w += 64) lds[m.lbase + w] = sum_g[w];
-            __builtin_amdgcn_wave_barrier();
+            m.sum_on = a.use_sum != 0 && d.sum_words > 0;
+            if (m.sum_on) {
+                const uint32_t *sum_g = reinterpret_cast<const uint32_t *>(a.ws + d.off_sum);
+                for (int32_t w = lane; w < d.sum_words; w += 64) lds[m.lbase + w] = sum_g[w];
+                __builtin_amdgcn_wave_barrier();
+            }
         }
         if constexpr (RES != RES_HBM) {
             for (uint32_t w = lane; w < m.occ_words; w += 64) lds[m.lbase + w] = prefilled ? m.occ_g[w] : 0u;
@@ -1372,7 +1380,6 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         // smax mode: the sweep runs on past n* and records the largest cluster
         // after every addition with win_lo <= r < win_hi
         const bool smax_mode = d.smax_mode != 0;
-        const bool periodic = d.periodic != 0;
         int32_t smax = a.state[sid].smax;
         uint32_t *win = reinterpret_cast<uint32_t *>(a.ws + d.off_win);
         // One addition done (r sites occupied, the new site's cluster has
@@ -1498,17 +1505,17 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         BandCursor bc;
         bc.init(reinterpret_cast<const uint32_t *>(a.ws + d.off_counts),
                 reinterpret_cast<const uint32_t *>(a.ws + d.off_sites), cap, nb);
-        SiteStep<NCH> cur, nxt;
+        SiteStep<NCH, PER> cur, nxt;
         uint32_t pc = 0;
         int got = bc.next(pc, lane);
         if (got < 0) status = NZ_ST_BUCKET;
         if constexpr (kLookahead<NCH>) {
-            if (got == 1) cur.prepare(m, lds, pc, L, ostride, ocode, periodic);
+            if (got == 1) cur.prepare(m, lds, pc, L, ostride, ocode);
             while (got == 1) {
                 ++r;
                 uint32_t pcn = 0;
                 const int gotn = bc.next(pcn, lane);
-                if (gotn == 1) nxt.prepare(m, lds, pcn, L, ostride, ocode, periodic);
+                if (gotn == 1) nxt.prepare(m, lds, pcn, L, ostride, ocode);
                 uint32_t total, flags;
                 sweep_step<NCH, RES>(m, lds, cur, ostride, ocode, L, dcap, total, flags);
                 if (finished(total, flags)) break;
@@ -1522,7 +1529,7 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         } else {
             while (got == 1) {
                 ++r;
-                cur.prepare(m, lds, pc, L, ostride, ocode, periodic);
+                cur.prepare(m, lds, pc, L, ostride, ocode);
                 uint32_t total, flags;
                 sweep_step<NCH, RES>(m, lds, cur, ostride, ocode, L, dcap, total, flags);
                 if (finished(total, flags)) break;
@@ -1799,7 +1806,7 @@ __device__ __forceinline__ int32_t wrap_merge(uint64_t *pw, int D, int32_t lroot
 // new site's displacement from each neighbouring root carried along and
 // compared whenever two neighbours share a root.
 template <int NCH>
-__device__ __forceinline__ void wrap_step(uint32_t *occ, uint64_t *pw, const SiteStep<NCH> &cur, const int32_t (&od0)[NCH],
+__device__ __forceinline__ void wrap_step(uint32_t *occ, uint64_t *pw, const SiteStep<NCH, true> &cur, const int32_t (&od0)[NCH],
                                           const int32_t (&ostride)[NCH], const uint32_t (&ocode)[NCH], int32_t L,
                                           int dcap, uint32_t &total, uint32_t &flags)
 {
@@ -1903,12 +1910,12 @@ __global__ __launch_bounds__(256) void nz_wrap_sweep_kernel(NzSweepArgs a, Sweep
         BandCursor bc;
         bc.init(reinterpret_cast<const uint32_t *>(a.ws + d.off_counts),
                 reinterpret_cast<const uint32_t *>(a.ws + d.off_sites), static_cast<uint32_t>(d.cap), d.nb);
-        SiteStep<NCH> cur;
+        SiteStep<NCH, true> cur;
         uint32_t pc = 0;
         int got = bc.next(pc, lane);
         while (got == 1) {
             ++r;
-            cur.prepare(m, nullptr, pc, L, ostride, ocode, true);
+            cur.prepare(m, nullptr, pc, L, ostride, ocode);
             uint32_t total, flags;
             wrap_step<NCH>(m.occ_g, pw, cur, od0, ostride, ocode, L, a.dcap, total, flags);
             if (flags == NZ_FLAGS) {
@@ -2018,11 +2025,11 @@ hipError_t launch_winsum(const NzSample *desc, const NzState *state, int32_t nsa
     return hipGetLastError();
 }
 
-template <int NCH, int RES, bool BLOCK, int FB = NCH>
+template <int NCH, int RES, bool BLOCK, bool PER, int FB = NCH>
 static hipError_t launch_sweep_t(const NzSweepArgs &a, const SweepOut &o, int grid, int wg_waves, size_t lds,
                                  hipStream_t st)
 {
-    auto k = nz_sweep_kernel<NCH, RES, BLOCK, FB>;
+    auto k = nz_sweep_kernel<NCH, RES, BLOCK, FB, PER>;
     if (lds > 65536) {
         hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                            static_cast<int>(lds));
@@ -2032,20 +2039,20 @@ static hipError_t launch_sweep_t(const NzSweepArgs &a, const SweepOut &o, int gr
     return hipGetLastError();
 }
 
-template <int RES, bool BLOCK>
+template <int RES, bool BLOCK, bool PER = false>
 static hipError_t launch_sweep_r(int nch, bool wide_block, const NzSweepArgs &a, const SweepOut &o, int grid,
                                  int wg_waves, size_t lds, hipStream_t st)
 {
     switch (nch) {
-    case 1: return launch_sweep_t<1, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
-    case 2: return launch_sweep_t<2, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
-    case 4: return launch_sweep_t<4, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
-    case 8: return launch_sweep_t<8, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
+    case 1: return launch_sweep_t<1, RES, BLOCK, PER>(a, o, grid, wg_waves, lds, st);
+    case 2: return launch_sweep_t<2, RES, BLOCK, PER>(a, o, grid, wg_waves, lds, st);
+    case 4: return launch_sweep_t<4, RES, BLOCK, PER>(a, o, grid, wg_waves, lds, st);
+    case 8: return launch_sweep_t<8, RES, BLOCK, PER>(a, o, grid, wg_waves, lds, st);
     case 14:
         if constexpr (BLOCK) {
-            if (!wide_block) return launch_sweep_t<14, RES, BLOCK, 8>(a, o, grid, wg_waves, lds, st);
+            if (!wide_block) return launch_sweep_t<14, RES, BLOCK, PER, 8>(a, o, grid, wg_waves, lds, st);
         }
-        return launch_sweep_t<14, RES, BLOCK>(a, o, grid, wg_waves, lds, st);
+        return launch_sweep_t<14, RES, BLOCK, PER>(a, o, grid, wg_waves, lds, st);
     default: return hipErrorInvalidValue;
     }
 }
@@ -2067,11 +2074,20 @@ hipError_t launch_wrap_sweep(int nch, const NzSweepArgs &a, int32_t *nstar, int3
     return hipGetLastError();
 }
 
-hipError_t launch_sweep(int nch, bool wide_block, int residency, bool block, const NzSweepArgs &a, int32_t *nstar,
-                        int32_t *mass, const int32_t *out_index, int grid, int wg_waves, hipStream_t st)
+hipError_t launch_sweep(int nch, bool wide_block, int residency, bool block, bool periodic, const NzSweepArgs &a,
+                        int32_t *nstar, int32_t *mass, const int32_t *out_index, int grid, int wg_waves, hipStream_t st)
 {
     SweepOut o{nstar, mass, out_index};
     const size_t lds = static_cast<size_t>(a.lds_words) * 4u * static_cast<size_t>(wg_waves);
+    if (periodic) {
+        if (block) return hipErrorInvalidValue;
+        switch (residency) {
+        case RES_HBM: return launch_sweep_r<RES_HBM, false, true>(nch, false, a, o, grid, wg_waves, lds, st);
+        case RES_OCC: return launch_sweep_r<RES_OCC, false, true>(nch, false, a, o, grid, wg_waves, lds, st);
+        case RES_ALL: return launch_sweep_r<RES_ALL, false, true>(nch, false, a, o, grid, wg_waves, lds, st);
+        default: return hipErrorInvalidValue;
+        }
+    }
     if (block) {
         switch (residency) {
         case RES_HBM: return launch_sweep_r<RES_HBM, true>(nch, wide_block, a, o, grid, wg_waves, lds, st);

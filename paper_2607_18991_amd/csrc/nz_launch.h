@@ -35,8 +35,10 @@ hipError_t launch_winsum(const NzSample *desc, const NzState *state, int32_t nsa
 // slice must end with block_lds_words() words for the block's site table).
 // wide_block: some block sample has z > 512, so the block path's one-site
 // fallback needs all nch chunks (else it is compiled for at most 8).
-hipError_t launch_sweep(int nch, bool wide_block, int residency, bool block, const NzSweepArgs &a, int32_t *nstar,
-                        int32_t *mass, const int32_t *out_index, int grid, int wg_waves, hipStream_t st);
+// periodic: every sample of the chunk has periodic coordinates (largest-cluster
+// windows); such a chunk goes one site per step (block must be false).
+hipError_t launch_sweep(int nch, bool wide_block, int residency, bool block, bool periodic, const NzSweepArgs &a,
+                        int32_t *nstar, int32_t *mass, const int32_t *out_index, int grid, int wg_waves, hipStream_t st);
 uint32_t block_lds_words();
 
 // Periodic first-wrap sweep of a chunk whose samples all have wrap set; one

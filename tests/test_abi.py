@@ -58,6 +58,12 @@ def test_batch_rejects_bad_jobs():
     assert e.value.code == nz.NZ_EINVAL
     with pytest.raises(nz.NzError):
         nz.nz_batch_workspace_bytes([dict(L=4, zone_mask=1, seed=1, nsamples=1)], tune=dict(residency=7))
+    for summary in (-1, 3):
+        with pytest.raises(nz.NzError) as e:
+            nz.nz_batch_workspace_bytes([dict(L=4, zone_mask=1, seed=1, nsamples=1)], tune=dict(summary=summary))
+        assert e.value.code == nz.NZ_EINVAL
+    for summary in (0, 1, 2):
+        assert nz.nz_batch_workspace_bytes([dict(L=4, zone_mask=1, seed=1, nsamples=1)], tune=dict(summary=summary)) > 0
 
 
 def test_workspace_sizing_grows_with_samples():

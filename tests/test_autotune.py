@@ -68,3 +68,19 @@ def test_batch_entries_and_lds_guard():
         autotune.signature([dict(L=16, zone_mask=1, nsamples=10)])
     for c in autotune.batch_candidates():
         assert nz.nz_batch_workspace_bytes(many, c) > 0
+
+
+def test_summary_choice_kept_only_for_batches_like_the_timed_one():
+    """The summary's worth depends on how many samples share the chip: a class
+    entry's choice applies to batches no larger than the one it was timed on."""
+    table = {"format": autotune.FORMAT, "entries": {
+        "16:892": {"tune": {"residency": 2, "wg_waves": 1, "waves_per_simd": 8, "sweep_mode": 2, "summary": 2},
+                   "samples": 256}}}
+    small = [dict(L=16, zone_mask=0x7F, seed=1, nsamples=200)]
+    large = [dict(L=16, zone_mask=0x7F, seed=1, nsamples=4000)]
+    assert autotune.for_jobs(small, table)["summary"] == 2
+    assert "summary" not in autotune.for_jobs(large, table)
+    assert autotune.for_jobs(large, table)["sweep_mode"] == 2
+    hbm = [c for c in autotune.candidates(16) if c["residency"] == 2]
+    assert {c["summary"] for c in hbm} == {1, 2}
+    assert {c.get("summary") for c in autotune.batch_candidates()} == {1, 2}

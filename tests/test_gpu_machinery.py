@@ -89,6 +89,8 @@ def test_prefix_list_redo():
     dict(wg_waves=3), dict(bucket_log2=4), dict(bucket_log2=10), dict(residency=1, wg_waves=2),
     dict(sweep_mode=1), dict(sweep_mode=2), dict(sweep_mode=1, residency=1), dict(sweep_mode=1, residency=3),
     dict(sweep_mode=2, residency=3), dict(sweep_mode=2, residency=1, wg_waves=4),
+    dict(summary=1), dict(summary=2), dict(summary=1, sweep_mode=1), dict(summary=1, sweep_mode=2, wg_waves=4),
+    dict(summary=2, sweep_mode=2),
 ])
 def test_tuning_never_changes_results(tune):
     jobs = [dict(L=L, zone_mask=m, seed=99, nsamples=10) for L in (4, 6, 8) for m in (1, 0x07, 0x7F)]
