@@ -173,11 +173,17 @@ __global__ __launch_bounds__(256) void nz_clear_kernel(const NzSample *__restric
 // Keys, prefill occupancy and band bucketing.  A block covers
 // KEYS_THREADS * 2 * KEYS_ITERS consecutive sites of one sample; per iteration
 // each wave takes 128 consecutive sites, lane l the pair (2l, 2l + 1) that
-// shares one Philox block, so two ballots yield four bitset words.
+// shares one Philox block, so two ballots yield four bitset words.  Lane `it`
+// keeps iteration it's ballots; after the loop lane l builds word l & 3 of
+// iteration l >> 2, so the bit interleave runs once for all of a wave's words.
 
 constexpr int KEYS_THREADS = 256;
 constexpr int KEYS_ITERS = 8;
 constexpr int KEYS_SITES_PER_BLOCK = KEYS_THREADS * 2 * KEYS_ITERS;
+static_assert(4 * KEYS_ITERS <= 64, "one lane per bitset word of a wave's iterations");
+
+// Predicate code of an unsigned less-than for the lane-mask compare builtins.
+constexpr int kIcmpUlt = 36;
 
 // The 16 bits of x moved to the even bit positions of a 32-bit word.
 __device__ __forceinline__ uint32_t spread_even(uint32_t x)
@@ -268,32 +274,32 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
     uint32_t *qs = bq_site[wave];
     uint32_t nq = 0;        // wave-uniform
     const uint32_t block_base = static_cast<uint32_t>(blk) * KEYS_SITES_PER_BLOCK;
+    // even / odd prefill ballots of iteration it, held by lane it
+    uint32_t be_lo = 0, be_hi = 0, bo_lo = 0, bo_hi = 0;
+    int its = 0;            // iterations this wave ran (wave-uniform)
     for (int it = 0; it < KEYS_ITERS; ++it) {
         const uint32_t wbase = block_base + it * (2 * KEYS_THREADS) + 2u * (threadIdx.x & ~63u);
         if (wbase >= N) break;
+        its = it + 1;
         const uint32_t i0 = wbase + 2u * lane, i1 = i0 + 1u;
         uint64_t K0, K1;
         site_key_pair(seed_lo, seed_hi, smp_lo, smp_hi, i0 >> 1, K0, K1);
-        const bool v0 = i0 < N, v1 = i1 < N;
-        const bool pre0 = v0 && K0 < c.T0, pre1 = v1 && K1 < c.T0;
-        const bool band0 = v0 && !pre0 && (band_all || K0 < band_end);
-        const bool band1 = v1 && !pre1 && (band_all || K1 < band_end);
-        const uint64_t be = __ballot(pre0);
-        const uint64_t bo = __ballot(pre1);
-        const uint64_t qe = __ballot(band0);
-        const uint64_t qo = __ballot(band1);
-        // Word q of the four covering sites wbase .. wbase + 127 interleaves
-        // bits 16q .. 16q + 15 of the even and odd ballots.  Every lane stores
-        // (word lane & 3, identical values per address); words past the padded
-        // bitset are not stored.
-        const uint32_t q = lane & 3u;
-        const uint32_t e16 = static_cast<uint32_t>(be >> (16u * q)) & 0xFFFFu;
-        const uint32_t o16 = static_cast<uint32_t>(bo >> (16u * q)) & 0xFFFFu;
-        const uint32_t widx = (wbase >> 5) + q;
-        const uint32_t word = spread_even(e16) | (spread_even(o16) << 1);
-        if (widx < occ_words) occ[widx] = word;
-        // the block's prefilled words, in site order (chunk it * 4 + wave)
-        if (lane < 4u) pre_words[(static_cast<uint32_t>(it) * 4u + wave) * 4u + q] = word;
+        // lane masks of the compares (prefilled: key < T0; band: T0 <= key <
+        // band_end), combined on the scalar unit
+        const uint64_t vm0 = __builtin_amdgcn_uicmp(i0, N, kIcmpUlt);
+        const uint64_t vm1 = __builtin_amdgcn_uicmp(i1, N, kIcmpUlt);
+        const uint64_t be = vm0 & __builtin_amdgcn_uicmpl(K0, c.T0, kIcmpUlt);
+        const uint64_t bo = vm1 & __builtin_amdgcn_uicmpl(K1, c.T0, kIcmpUlt);
+        const uint64_t qe = (vm0 & ~be) & (band_all ? ~0ull : __builtin_amdgcn_uicmpl(K0, band_end, kIcmpUlt));
+        const uint64_t qo = (vm1 & ~bo) & (band_all ? ~0ull : __builtin_amdgcn_uicmpl(K1, band_end, kIcmpUlt));
+        const bool band0 = __builtin_amdgcn_inverse_ballot_w64(qe);
+        const bool band1 = __builtin_amdgcn_inverse_ballot_w64(qo);
+        if (lane == static_cast<uint32_t>(it)) {
+            be_lo = static_cast<uint32_t>(be);
+            be_hi = static_cast<uint32_t>(be >> 32);
+            bo_lo = static_cast<uint32_t>(bo);
+            bo_hi = static_cast<uint32_t>(bo >> 32);
+        }
         // band: queued, then bucketed in full waves
         const uint32_t nqe = static_cast<uint32_t>(__popcll(qe));
         if (band0) {
@@ -331,6 +337,27 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
         }
     }
     if (lane < nq) keys_bucket(c, qk[lane], qs[lane]);
+    {
+        // Word q of iteration it (sites wbase .. wbase + 127 of that iteration)
+        // interleaves bits 16q .. 16q + 15 of the even and odd ballots; lane
+        // 4 it + q builds it.  Words past the padded bitset are not stored.
+        const int src = static_cast<int>(lane >> 2);
+        const uint32_t q = lane & 3u;
+        const uint32_t elo = static_cast<uint32_t>(__shfl(static_cast<int>(be_lo), src));
+        const uint32_t ehi = static_cast<uint32_t>(__shfl(static_cast<int>(be_hi), src));
+        const uint32_t olo = static_cast<uint32_t>(__shfl(static_cast<int>(bo_lo), src));
+        const uint32_t ohi = static_cast<uint32_t>(__shfl(static_cast<int>(bo_hi), src));
+        const uint32_t sh = 16u * (q & 1u);
+        const uint32_t e16 = ((q < 2u ? elo : ehi) >> sh) & 0xFFFFu;
+        const uint32_t o16 = ((q < 2u ? olo : ohi) >> sh) & 0xFFFFu;
+        const uint32_t word = spread_even(e16) | (spread_even(o16) << 1);
+        const uint32_t widx = (block_base >> 5) + static_cast<uint32_t>(src) * (2u * KEYS_THREADS / 32u) + 4u * wave + q;
+        if (src < its) {
+            if (widx < occ_words) occ[widx] = word;
+            // the block's prefilled words, in site order (chunk it * 4 + wave)
+            pre_words[(static_cast<uint32_t>(src) * 4u + wave) * 4u + q] = word;
+        }
+    }
     if (d.T0 == 0) return;   // plain sample: nothing prefilled (uniform over the block)
     __syncthreads();
     // exclusive scan of the 128 word counts (waves 0 and 1, one word per lane)
