@@ -610,7 +610,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 const int32_t bx_hook = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(256, (max_site + 1023) / 1024)));
                 const int32_t bx_site = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(1024, (max_site + 1023) / 1024)));
                 HIP_TRY(nz::launch_prefill(d_desc, d_list, static_cast<int32_t>(prefill_list.size()), bx_hook, bx_site, d_tabs, ws,
-                                           d_state, smax != nullptr, wrap_chunk, st));
+                                           d_state, smax != nullptr, wrap_chunk, per_chunk, st));
                 // Resolve backoffs inside the chunk: samples whose bulk state already
                 // spans are re-keyed and re-labelled from n0 - b, and if that spans
                 // too from n0 - 3b, so they join this chunk's sweep instead of a
@@ -648,7 +648,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                         a = b;
                     }
                     HIP_TRY(nz::launch_prefill(d_desc, d_list, na, bx_hook, bx_site, d_tabs, ws, d_state, smax != nullptr,
-                                               wrap_chunk, st));
+                                               wrap_chunk, per_chunk, st));
                 }
             }
             if (pe) HIP_TRY(hipEventRecord(pe->ev[2], st));

@@ -538,6 +538,9 @@ constexpr int HOOK_UNROLL = 8;
 // most 1025 words).
 constexpr int32_t HOOK_SUM_MAX = 1025;
 
+// PER: periodic coordinates (compiled apart, so that the free-boundary hook
+// carries no wrap correction).
+template <bool PER>
 __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
                                                       int32_t nlist, int32_t bx, const NzOffset *__restrict__ tabs,
                                                       uint8_t *__restrict__ ws, NzState *__restrict__ state)
@@ -562,7 +565,6 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
     const int32_t L = d.L;
     const int32_t zh = d.z >> 1;
     const uint64_t magic = d.magic;
-    const bool periodic = d.periodic != 0;
     int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_parc);
     const uint32_t *occ = reinterpret_cast<const uint32_t *>(ws + d.off_occ);
     const uint32_t *wpos = reinterpret_cast<const uint32_t *>(ws + d.off_wpos);
@@ -585,8 +587,14 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
                 o.code = 0xFFFFFFFFu;
                 if (k0 + q < zh) o = tab[k0 + q];
                 const uint32_t out = o.code & ~A;
-                const bool ok = out == 0u || (periodic && (o.code & ~kCodeBits) == 0u);
-                t[q] = s + o.stride + (periodic && out ? wrap_fix(out, L) : 0);
+                bool ok;
+                if constexpr (PER) {
+                    ok = (o.code & ~kCodeBits) == 0u;   // every offset wraps back in, padding aside
+                    t[q] = s + o.stride + (out ? wrap_fix(out, L) : 0);
+                } else {
+                    ok = out == 0u;
+                    t[q] = s + o.stride;
+                }
                 const uint32_t wi = static_cast<uint32_t>(t[q]) >> 5;
                 const bool maybe = !use_sum || ((hsum[(wi >> gs) >> 5] >> ((wi >> gs) & 31)) & 1u);
                 w[q] = ok && maybe ? occ[wi] : 0u;
@@ -2015,7 +2023,8 @@ hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int3
 }
 
 hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nlist, int32_t bx_hook, int32_t bx_site,
-                          const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, bool wrap, hipStream_t st)
+                          const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, bool wrap, bool periodic,
+                          hipStream_t st)
 {
     if (nlist <= 0) return hipSuccess;
     const uint32_t slots8 = static_cast<uint32_t>((nlist + 7) / 8) * 8u;
@@ -2028,8 +2037,12 @@ hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nli
                            nlist, bx_site, ws, state);
         return hipGetLastError();
     }
-    hipLaunchKernelGGL(nz_hook_kernel, dim3(static_cast<uint32_t>(bx_hook) * slots8), dim3(256), 0, st, desc, list, nlist,
-                       bx_hook, tabs, ws, state);
+    if (periodic)
+        hipLaunchKernelGGL(nz_hook_kernel<true>, dim3(static_cast<uint32_t>(bx_hook) * slots8), dim3(256), 0, st, desc, list,
+                           nlist, bx_hook, tabs, ws, state);
+    else
+        hipLaunchKernelGGL(nz_hook_kernel<false>, dim3(static_cast<uint32_t>(bx_hook) * slots8), dim3(256), 0, st, desc,
+                           list, nlist, bx_hook, tabs, ws, state);
     hipLaunchKernelGGL(nz_compress_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
                        nlist, bx_site, ws, state);
     hipLaunchKernelGGL(nz_accum_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list, nlist,

@@ -23,8 +23,10 @@ hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int3
 // Bulk connected components for the samples listed in list[0..nlist).
 // smax: also the largest cluster of each smax-mode sample's prefilled state.
 // wrap: the listed samples are periodic first-wrap samples (64-bit entries).
+// periodic: the listed samples have periodic coordinates (all or none of them).
 hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nlist, int32_t bx_hook, int32_t bx_site,
-                          const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, bool wrap, hipStream_t st);
+                          const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, bool wrap, bool periodic,
+                          hipStream_t st);
 
 // out[0..w) += sum over the chunk's finished samples 0..nsamp-1 of their S_max windows.
 hipError_t launch_winsum(const NzSample *desc, const NzState *state, int32_t nsamp, int32_t w, const uint8_t *ws,
