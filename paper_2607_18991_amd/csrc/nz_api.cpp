@@ -874,6 +874,9 @@ NZ_API int nz_last_batch_timing(double ms[6])
 // other's keys and labelling.  Each group gets its own share of the workspace.
 
 constexpr int64_t kSplitMinSamples = 512;
+// widest neighbourhood of the first group (L = 16, 7 compact masks x 1000,
+// learned: 47.0 ms with z <= 64, 47.5 with z <= 130, 49.9 with z <= 220)
+constexpr int32_t kSplitZ = 64;
 
 struct SplitPlan {
     std::vector<nz_job> job[2];
@@ -887,7 +890,7 @@ bool split_groups(const nz_job *jobs, int32_t njobs, const Tune &tune, SplitPlan
     if (getenv("NZ_DEBUG_NO_SPLIT")) return false;
     int64_t o = 0, count[2] = {0, 0};
     for (int j = 0; j < njobs; ++j) {
-        const int g = coordination(jobs[j].zone_mask) <= 64 ? 0 : 1;
+        const int g = coordination(jobs[j].zone_mask) <= kSplitZ ? 0 : 1;
         if (jobs[j].nsamples > 0) {
             sp.job[g].push_back(jobs[j]);
             sp.index[g].push_back(j);
