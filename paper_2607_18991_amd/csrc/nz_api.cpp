@@ -73,7 +73,7 @@ int64_t pow5(int64_t L) { return L * L * L * L * L; }
 // vectors whose last non-zero coordinate is negative and then their negations
 // in the same order, so its first half holds one vector of every +-d pair.
 
-std::vector<std::array<int, 5>> zone_vectors(uint32_t mask)
+std::vector<std::array<int, 5>> enumerate_zone_vectors(uint32_t mask)
 {
     std::vector<std::array<int, 5>> neg;
     for (int k = 1; k <= 7; ++k) {
@@ -99,6 +99,18 @@ std::vector<std::array<int, 5>> zone_vectors(uint32_t mask)
     std::vector<std::array<int, 5>> all = neg;
     for (const auto &d : neg) all.push_back({-d[0], -d[1], -d[2], -d[3], -d[4]});
     return all;
+}
+
+// The vectors of every mask 1..127, enumerated once per process (mask 0 and
+// masks above 127 give the empty list).
+const std::vector<std::array<int, 5>> &zone_vectors(uint32_t mask)
+{
+    static const std::array<std::vector<std::array<int, 5>>, 128> all = [] {
+        std::array<std::vector<std::array<int, 5>>, 128> t;
+        for (uint32_t m = 1; m < 128; ++m) t[m] = enumerate_zone_vectors(m);
+        return t;
+    }();
+    return all[mask < 128 ? mask : 0];
 }
 
 // z(mask) for every mask, enumerated once.
@@ -295,6 +307,27 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
     return s;
 }
 
+// plan_sizes of consecutive plans that share its inputs (the samples of one
+// job do) is computed once.
+struct SizesMemo {
+    bool have = false;
+    Plan key{};
+    int bucket_log2 = 0;
+    Sizes s{};
+    const Sizes &get(const Plan &p, int bl)
+    {
+        if (!have || bl != bucket_log2 || p.L != key.L || p.n0 != key.n0 || p.backoff != key.backoff ||
+            p.band_hi != key.band_hi || p.shift_adj != key.shift_adj || p.prefix_mul != key.prefix_mul ||
+            p.wrap != key.wrap || p.win_lo != key.win_lo || p.win_hi != key.win_hi) {
+            s = plan_sizes(p, bl);
+            key = p;
+            bucket_log2 = bl;
+            have = true;
+        }
+        return s;
+    }
+};
+
 int64_t default_band_hi(int32_t L, uint32_t mask, int64_t n0)
 {
     const int64_t N = pow5(L);
@@ -434,6 +467,11 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
     // tables for every (mask, L) of the batch live at the start of the workspace
     TablePool pool;
     std::vector<Plan> todo;
+    {
+        int64_t total = 0;
+        for (int j = 0; j < njobs; ++j) total += std::max<int64_t>(0, jobs[j].nsamples);
+        todo.reserve(static_cast<size_t>(std::min<int64_t>(total, 0x7FFFFFFF)));
+    }
     int64_t out = 0;
     for (int j = 0; j < njobs; ++j) {
         const nz_job &J = jobs[j];
@@ -475,6 +513,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             return a.per != b.per ? b.per : a.prio > b.prio;
         });
         std::vector<Plan> redo;
+        SizesMemo memo;
         size_t pos = 0;
         while (pos < todo.size()) {
             // ---- form a chunk: longest first, as many as the workspace holds
@@ -486,7 +525,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             size_t used = head;
             while (pos < todo.size() && static_cast<int32_t>(chunk.size()) < cmax) {
                 if (!chunk.empty() && todo[pos].per != chunk.front().per) break;
-                Sizes s = plan_sizes(todo[pos], tune.bucket_log2);
+                const Sizes &s = memo.get(todo[pos], tune.bucket_log2);
                 if (used + s.total > ws_bytes) break;
                 used += s.total;
                 chunk.push_back(todo[pos]);
@@ -515,6 +554,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             uint32_t max_N = 0;
             int64_t max_site = 0;
             std::vector<int32_t> desc_of_chunk(n);
+            uint32_t last_mask = 0;   // offset table of the previous descriptor's (mask, L)
+            int32_t last_L = 0, last_tab = 0, last_z = 0;
             for (int32_t di = 0; di < n; ++di) {
                 const int32_t ci = byL[di];
                 const Plan &p = chunk[ci];
@@ -532,7 +573,13 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 d.shift = s.shift;
                 d.full = s.full;
                 d.prefix_cap = s.prefix_cap;
-                d.tab = pool.get(p.mask, p.L, &d.z);
+                if (p.mask != last_mask || p.L != last_L) {
+                    last_tab = pool.get(p.mask, p.L, &last_z);
+                    last_mask = p.mask;
+                    last_L = p.L;
+                }
+                d.tab = last_tab;
+                d.z = last_z;
                 d.magic = p.L == 1 ? 0 : static_cast<uint64_t>(~0ull / static_cast<uint64_t>(p.L) + 1ull);
                 d.off_par = off; off += s.par;
                 d.off_occ = off; off += s.occ;
@@ -791,13 +838,17 @@ size_t batch_bytes(const nz_job *jobs, int32_t njobs, const Tune &tune)
 {
     // all samples of the first chunk resident, plus room for one redo of the
     // largest sample with a full band
-    std::vector<size_t> per;
-    TablePool pool;
+    std::vector<std::pair<size_t, int64_t>> per;   // (bytes of one sample, samples) of every job
+    std::vector<std::pair<uint32_t, int32_t>> tables;
+    size_t tab_entries = 0;
     int32_t maxL = 1;
     bool any_wrap = false;
     for (int j = 0; j < njobs; ++j) {
-        int32_t z;
-        pool.get(jobs[j].zone_mask, jobs[j].L, &z);
+        const auto key = std::make_pair(jobs[j].zone_mask, jobs[j].L);
+        if (std::find(tables.begin(), tables.end(), key) == tables.end()) {
+            tables.push_back(key);
+            tab_entries += static_cast<size_t>(coordination(jobs[j].zone_mask));
+        }
         any_wrap = any_wrap || jobs[j].boundary == NZ_PERIODIC;
         Plan p{};
         p.L = jobs[j].L;
@@ -809,14 +860,20 @@ size_t batch_bytes(const nz_job *jobs, int32_t njobs, const Tune &tune)
         p.band_hi = jobs[j].band_hi > 0 ? std::min<int64_t>(jobs[j].band_hi, N) : default_band_hi(p.L, p.mask, p.n0);
         if (p.band_hi <= p.n0) p.band_hi = std::min<int64_t>(N, p.n0 + 4096);
         p.prefix_mul = 1;
-        const size_t s = plan_sizes(p, tune.bucket_log2).total;
-        for (int64_t k = 0; k < jobs[j].nsamples && static_cast<int64_t>(per.size()) < 4 * kMaxChunk; ++k) per.push_back(s);
+        if (jobs[j].nsamples > 0) per.emplace_back(plan_sizes(p, tune.bucket_log2).total, jobs[j].nsamples);
         maxL = std::max(maxL, jobs[j].L);
     }
-    std::sort(per.begin(), per.end(), std::greater<size_t>());
-    const size_t count = std::min<size_t>(per.size(), kMaxChunk);
-    size_t total = header_bytes(pool.entries.size(), static_cast<int32_t>(std::max<size_t>(count, 1)));
-    for (size_t k = 0; k < count; ++k) total += per[k];
+    // the kMaxChunk largest samples
+    std::sort(per.begin(), per.end(), [](const auto &a, const auto &b) { return a.first > b.first; });
+    int64_t count = 0;
+    size_t sum = 0;
+    for (const auto &e : per) {
+        const int64_t take = std::min<int64_t>(e.second, kMaxChunk - count);
+        sum += e.first * static_cast<size_t>(take);
+        count += take;
+        if (count == kMaxChunk) break;
+    }
+    size_t total = header_bytes(tab_entries, static_cast<int32_t>(std::max<int64_t>(count, 1))) + sum;
     Plan full{};
     full.L = maxL;
     full.mask = 127;
