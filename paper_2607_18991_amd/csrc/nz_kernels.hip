@@ -425,10 +425,12 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
 }
 
 // ---------------------------------------------------------------------------
-// Bucket sort: one workgroup per (sample, bucket); bitonic network in LDS over
-// (key, packed site) pairs padded to a power of two; sorted packed sites are
-// written back in place.  Over-full buckets are left alone (the sweep reports
-// them if it reaches one).
+// Bucket sort: one wave per (sample, bucket); bitonic network in the wave's
+// LDS slice over (key, packed site) pairs padded to a power of two, each lane
+// taking whole compare-exchange pairs, stages ordered by the wave's own LDS
+// ordering (no workgroup barrier); sorted packed sites are written back in
+// place.  Over-full buckets are left alone (the sweep reports them if it
+// reaches one).
 
 constexpr int SORT_THREADS = 256;
 
@@ -437,27 +439,31 @@ __device__ __forceinline__ bool pair_greater(uint64_t ka, uint32_t pa, uint64_t 
     return ka > kb || (ka == kb && pa > pb);
 }
 
+// slice: LDS entries per wave (a power of two >= every bucket's capacity)
 __global__ __launch_bounds__(SORT_THREADS) void nz_sort_kernel(const NzSample *__restrict__ desc, int32_t nsamp,
-                                                               int32_t max_nb, uint8_t *__restrict__ ws)
+                                                               int32_t max_nb, uint32_t slice, uint8_t *__restrict__ ws)
 {
     extern __shared__ uint64_t sort_lds[];
-    const int64_t items = static_cast<int64_t>(nsamp) * max_nb;
-    for (int64_t item = blockIdx.x; item < items; item += gridDim.x) {
-        const int sid = static_cast<int>(item / max_nb);
-        const int b = static_cast<int>(item % max_nb);
+    const uint32_t lane = lane_id();
+    const uint32_t waves = blockDim.x >> 6;
+    const uint32_t wave = threadIdx.x >> 6;
+    uint64_t *k = sort_lds + static_cast<size_t>(wave) * slice;
+    uint32_t *p = reinterpret_cast<uint32_t *>(sort_lds + static_cast<size_t>(waves) * slice) + static_cast<size_t>(wave) * slice;
+    const uint32_t items = static_cast<uint32_t>(nsamp) * static_cast<uint32_t>(max_nb);
+    for (uint32_t item = blockIdx.x * waves + wave; item < items; item += gridDim.x * waves) {
+        const int sid = static_cast<int>(item / static_cast<uint32_t>(max_nb));
+        const int b = static_cast<int>(item - static_cast<uint32_t>(sid) * static_cast<uint32_t>(max_nb));
         const NzSample &d = desc[sid];
         if (b >= d.nb) continue;
         const uint32_t *counts = reinterpret_cast<const uint32_t *>(ws + d.off_counts);
         const uint32_t cnt = counts[b];
         const uint32_t cap = static_cast<uint32_t>(d.cap);
         if (cnt <= 1u || cnt > cap) continue;
-        uint32_t P = 1;
+        uint32_t P = 2;
         while (P < cnt) P <<= 1;
-        uint64_t *k = sort_lds;
-        uint32_t *p = reinterpret_cast<uint32_t *>(sort_lds + P);
         const uint64_t *gk = reinterpret_cast<const uint64_t *>(ws + d.off_keys) + static_cast<uint64_t>(b) * cap;
         uint32_t *gp = reinterpret_cast<uint32_t *>(ws + d.off_sites) + static_cast<uint64_t>(b) * cap;
-        for (uint32_t i = threadIdx.x; i < P; i += SORT_THREADS) {
+        for (uint32_t i = lane; i < P; i += 64u) {
             if (i < cnt) {
                 k[i] = gk[i];
                 p[i] = gp[i];
@@ -466,26 +472,27 @@ __global__ __launch_bounds__(SORT_THREADS) void nz_sort_kernel(const NzSample *_
                 p[i] = ~0u;
             }
         }
-        __syncthreads();
+        __builtin_amdgcn_wave_barrier();
+        const uint32_t half = P >> 1;
         for (uint32_t size = 2; size <= P; size <<= 1) {
             for (uint32_t stride = size >> 1; stride > 0; stride >>= 1) {
-                for (uint32_t i = threadIdx.x; i < P; i += SORT_THREADS) {
-                    const uint32_t j = i ^ stride;
-                    if (j > i) {
-                        const bool up = (i & size) == 0;
-                        const uint64_t ki = k[i], kj = k[j];
-                        const uint32_t pi = p[i], pj = p[j];
-                        if (pair_greater(ki, pi, kj, pj) == up) {
-                            k[i] = kj; k[j] = ki;
-                            p[i] = pj; p[j] = pi;
-                        }
+                // pair q: i has bit `stride` clear, j = i + stride
+                for (uint32_t q = lane; q < half; q += 64u) {
+                    const uint32_t i = ((q & ~(stride - 1u)) << 1) | (q & (stride - 1u));
+                    const uint32_t j = i | stride;
+                    const bool up = (i & size) == 0u;
+                    const uint64_t ki = k[i], kj = k[j];
+                    const uint32_t pi = p[i], pj = p[j];
+                    if (pair_greater(ki, pi, kj, pj) == up) {
+                        k[i] = kj; k[j] = ki;
+                        p[i] = pj; p[j] = pi;
                     }
                 }
-                __syncthreads();
+                __builtin_amdgcn_wave_barrier();
             }
         }
-        for (uint32_t i = threadIdx.x; i < cnt; i += SORT_THREADS) gp[i] = p[i];
-        __syncthreads();
+        for (uint32_t i = lane; i < cnt; i += 64u) gp[i] = p[i];
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
@@ -2013,12 +2020,23 @@ hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int3
                        hipStream_t st)
 {
     if (nsamp <= 0 || max_nb <= 0) return hipSuccess;
-    uint32_t P = 1;
+    uint32_t P = 2;
     while (P < static_cast<uint32_t>(max_cap)) P <<= 1;
-    const size_t lds = static_cast<size_t>(P) * (sizeof(uint64_t) + sizeof(uint32_t));
     const int64_t items = static_cast<int64_t>(nsamp) * max_nb;
-    const uint32_t grid = static_cast<uint32_t>(items < 65536 * 4 ? items : 65536 * 4);
-    hipLaunchKernelGGL(nz_sort_kernel, dim3(grid), dim3(SORT_THREADS), lds, st, desc, nsamp, max_nb, ws);
+    if (items > 0x7FFFFFFFll) return hipErrorInvalidValue;   // the waves step through items in 32 bits
+    // one wave per bucket; as many waves per workgroup as 64 KB of LDS holds
+    const size_t per_wave = static_cast<size_t>(P) * (sizeof(uint64_t) + sizeof(uint32_t));
+    const int waves = static_cast<int>(std::max<size_t>(1, std::min<size_t>(SORT_THREADS / 64, 65536 / per_wave)));
+    const size_t lds = per_wave * static_cast<size_t>(waves);
+    auto k = nz_sort_kernel;
+    if (lds > 65536) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void *>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                           static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    const int64_t blocks = (items + waves - 1) / waves;
+    const uint32_t grid = static_cast<uint32_t>(blocks < 65536 * 4 ? blocks : 65536 * 4);
+    hipLaunchKernelGGL(k, dim3(grid), dim3(64 * waves), lds, st, desc, nsamp, max_nb, P, ws);
     return hipGetLastError();
 }
 
