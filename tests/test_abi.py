@@ -66,6 +66,16 @@ def test_batch_rejects_bad_jobs():
         assert nz.nz_batch_workspace_bytes([dict(L=4, zone_mask=1, seed=1, nsamples=1)], tune=dict(summary=summary)) > 0
 
 
+def test_workspace_sizing_counts_jobs_after_many_samples():
+    """The resident first chunk is sized from the largest samples of the whole
+    batch, also when a large job comes after more than 65536 small samples."""
+    small = dict(L=2, zone_mask=1, seed=1, nsamples=70000)
+    large = dict(L=16, zone_mask=1, seed=2, nsamples=64)
+    both = nz.nz_batch_workspace_bytes([small, large])
+    assert both >= nz.nz_batch_workspace_bytes([large])
+    assert both >= nz.nz_batch_workspace_bytes([large, small])
+
+
 def test_workspace_sizing_grows_with_samples():
     a = nz.nz_batch_workspace_bytes([dict(L=8, zone_mask=1, seed=1, nsamples=10)])
     b = nz.nz_batch_workspace_bytes([dict(L=8, zone_mask=1, seed=1, nsamples=100)])
