@@ -353,6 +353,9 @@ struct Tune {
     int dcap = 64;
     int sweep_mode = 0;
     int summary = 0;
+    // keys launch: one workgroup per block of sites (false), or as many
+    // workgroups as the CUs hold at once, each looping over blocks (true)
+    bool keys_resident = false;
 };
 
 int check_job(const nz_job &j, int idx)
@@ -551,6 +554,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             size_t off = head;
             int32_t max_nb = 0, max_cap = 0, max_z = 0, max_sum = 0;
             const bool use_sum = tune.summary == 1 || (tune.summary == 0 && n >= kSumSamplesPerCu * dev.cus);
+            const int32_t keys_grid = tune.keys_resident ? nz::keys_resident_wgs() * dev.cus : 0;
             uint32_t max_N = 0;
             int64_t max_site = 0;
             std::vector<int32_t> desc_of_chunk(n);
@@ -649,7 +653,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             for (int32_t a = 0; a < n;) {
                 int32_t b = a;
                 while (b < n && desc[b].N == desc[a].N) ++b;
-                HIP_TRY(nz::launch_keys(d_desc, nullptr, a, b - a, desc[a].N, ws, d_state, st));
+                HIP_TRY(nz::launch_keys(d_desc, nullptr, a, b - a, desc[a].N, ws, d_state, keys_grid, st));
                 a = b;
             }
             if (pe) HIP_TRY(hipEventRecord(pe->ev[1], st));
@@ -691,7 +695,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                     for (int32_t a = 0; a < na;) {
                         int32_t b = a;
                         while (b < na && desc[again[b]].N == desc[again[a]].N) ++b;
-                        HIP_TRY(nz::launch_keys(d_desc, d_list, a, b - a, desc[again[a]].N, ws, d_state, st));
+                        HIP_TRY(nz::launch_keys(d_desc, d_list, a, b - a, desc[again[a]].N, ws, d_state, keys_grid, st));
                         a = b;
                     }
                     HIP_TRY(nz::launch_prefill(d_desc, d_list, na, bx_hook, bx_site, d_tabs, ws, d_state, smax != nullptr,
@@ -991,6 +995,13 @@ int run_split(SplitPlan &sp, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_
                                           (sp.bytes[0] + sp.bytes[1])) / kAlign * kAlign;
     std::vector<int32_t> back[2];
     for (int g = 0; g < 2; ++g) back[g].assign(sp.job[g].size(), 0);
+    // Side by side, each group's keys launch keeps the CU slots it is given:
+    // with a workgroup per block of sites, the short keys workgroups would hand
+    // their slots one by one to the other group's long-lived labelling and
+    // sweep workgroups (L = 16 learned step: 46.5 -> 43.0 ms; a batch that
+    // runs as one group is faster with a workgroup per block).
+    Tune ts = tune;
+    ts.keys_resident = true;
     // the second group starts after the work already queued on the caller's stream
     HIP_TRY(hipEventRecord(side->start, st));
     HIP_TRY(hipStreamWaitEvent(side->st, side->start, 0));
@@ -1006,7 +1017,7 @@ int run_split(SplitPlan &sp, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_
             } else {
                 g_timing = timing;
                 rc_b = run_batch(sp.job[1].data(), static_cast<int32_t>(sp.job[1].size()), ws + wa, ws_bytes - wa,
-                                 d_nstar, d_mass, back[1].data(), tune, side->st, nullptr, sp.out[1].data());
+                                 d_nstar, d_mass, back[1].data(), ts, side->st, nullptr, sp.out[1].data());
             }
         } catch (...) {
             rc_b = fail(NZ_ENOMEM, "host allocation failed");
@@ -1020,7 +1031,7 @@ int run_split(SplitPlan &sp, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_
     int rc_a;
     try {
         rc_a = run_batch(sp.job[0].data(), static_cast<int32_t>(sp.job[0].size()), ws, wa, d_nstar, d_mass,
-                         back[0].data(), tune, st, nullptr, sp.out[0].data());
+                         back[0].data(), ts, st, nullptr, sp.out[0].data());
     } catch (...) {
         rc_a = fail(NZ_ENOMEM, "host allocation failed");
     }

@@ -223,10 +223,9 @@ __device__ __forceinline__ void keys_bucket(const KeysCtx &c, uint64_t K, uint32
     }
 }
 
-__global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *__restrict__ desc,
-                                                               const int32_t *__restrict__ list, int32_t first,
-                                                               int32_t blocks_per_sample, uint8_t *__restrict__ ws,
-                                                               NzState *__restrict__ state)
+__device__ __forceinline__ void keys_block(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
+                                           int32_t first, int32_t blocks_per_sample, uint8_t *__restrict__ ws,
+                                           NzState *__restrict__ state, int32_t vblock)
 {
     // The prefilled sites of this block are appended to the sample's list in
     // site order, with one global atomic per block: their bitset words are kept
@@ -239,9 +238,9 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
     __shared__ uint32_t pre_base;
     __shared__ uint64_t bq_key[KEYS_THREADS / 64][KEYS_BQ];
     __shared__ uint32_t bq_site[KEYS_THREADS / 64][KEYS_BQ];
-    const int which = static_cast<int>(blockIdx.x) / blocks_per_sample;
+    const int which = vblock / blocks_per_sample;
     const int sid = list ? list[first + which] : first + which;
-    const int blk = static_cast<int>(blockIdx.x) % blocks_per_sample;
+    const int blk = vblock % blocks_per_sample;
     const NzSample &d = desc[sid];
     const uint32_t N = static_cast<uint32_t>(d.N);
     const uint32_t seed_lo = static_cast<uint32_t>(d.seed), seed_hi = static_cast<uint32_t>(d.seed >> 32);
@@ -421,6 +420,19 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
             else parc[pos] = static_cast<int32_t>(pos);
         }
         ++pos;
+    }
+}
+
+// Workgroup g takes the blocks g, g + gridDim.x, ... of the launch (one pass
+// when the grid has a workgroup per block).
+__global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *__restrict__ desc,
+                                                               const int32_t *__restrict__ list, int32_t first,
+                                                               int32_t blocks_per_sample, int32_t nblocks,
+                                                               uint8_t *__restrict__ ws, NzState *__restrict__ state)
+{
+    for (int32_t vb = static_cast<int32_t>(blockIdx.x); vb < nblocks; vb += static_cast<int32_t>(gridDim.x)) {
+        keys_block(desc, list, first, blocks_per_sample, ws, state, vb);
+        __syncthreads();   // the next block reuses the LDS
     }
 }
 
@@ -2003,18 +2015,26 @@ hipError_t launch_clear(const NzSample *desc, const int32_t *list, int32_t nsamp
 }
 
 hipError_t launch_keys(const NzSample *desc, const int32_t *list, int32_t first, int32_t count, int32_t N, uint8_t *ws,
-                       NzState *state, hipStream_t st)
+                       NzState *state, int32_t max_grid, hipStream_t st)
 {
     if (count <= 0) return hipSuccess;
     const int32_t bps = (N + KEYS_SITES_PER_BLOCK - 1) / KEYS_SITES_PER_BLOCK;
     const int64_t blocks = static_cast<int64_t>(bps) * count;
     if (blocks > 0x7FFFFFFF) return hipErrorInvalidValue;
-    hipLaunchKernelGGL(nz_keys_kernel, dim3(static_cast<uint32_t>(blocks)), dim3(KEYS_THREADS), 0, st, desc, list, first,
-                       bps, ws, state);
+    const int64_t grid = max_grid > 0 ? std::min<int64_t>(blocks, max_grid) : blocks;
+    hipLaunchKernelGGL(nz_keys_kernel, dim3(static_cast<uint32_t>(grid)), dim3(KEYS_THREADS), 0, st, desc, list, first,
+                       bps, static_cast<int32_t>(blocks), ws, state);
     return hipGetLastError();
 }
 
 int32_t keys_sites_per_block() { return KEYS_SITES_PER_BLOCK; }
+
+int32_t keys_resident_wgs()
+{
+    int n = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, nz_keys_kernel, KEYS_THREADS, 0) != hipSuccess || n < 1) n = 1;
+    return n;
+}
 
 hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int32_t max_cap, uint8_t *ws,
                        hipStream_t st)

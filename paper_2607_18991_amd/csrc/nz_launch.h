@@ -13,8 +13,11 @@ hipError_t launch_clear(const NzSample *desc, const int32_t *list, int32_t nsamp
 // Keys for samples [first, first + count) of the descriptor array, all of
 // lattice size N.
 // (list != NULL: samples list[first .. first + count) instead).
+// max_grid > 0: at most that many workgroups, each taking several blocks.
+// keys_resident_wgs(): workgroups of the keys kernel one CU holds at once.
+int32_t keys_resident_wgs();
 hipError_t launch_keys(const NzSample *desc, const int32_t *list, int32_t first, int32_t count, int32_t N, uint8_t *ws,
-                       NzState *state, hipStream_t st);
+                       NzState *state, int32_t max_grid, hipStream_t st);
 int32_t keys_sites_per_block();
 
 hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int32_t max_cap, uint8_t *ws,
