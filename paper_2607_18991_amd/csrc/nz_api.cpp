@@ -936,7 +936,9 @@ NZ_API int nz_last_batch_timing(double ms[6])
 
 constexpr int64_t kSplitMinSamples = 512;
 // widest neighbourhood of the first group (L = 16, 7 compact masks x 1000,
-// learned: 47.0 ms with z <= 64, 47.5 with z <= 130, 49.9 with z <= 220)
+// learned: 47.0 ms with z <= 64, 47.5 with z <= 130, 49.9 with z <= 220;
+// with the keys launches keeping their slots: 43.0 ms with z <= 64, 44.1 with
+// z <= 10, 45.7 with z <= 130)
 constexpr int32_t kSplitZ = 64;
 
 struct SplitPlan {
