@@ -353,7 +353,7 @@ struct Tune {
     int dcap = 64;
     int sweep_mode = 0;
     int summary = 0;
-    // keys launch: one workgroup per block of sites (false), or as many
+    // keys launch: one workgroup per block of sites (false), or half as many
     // workgroups as the CUs hold at once, each looping over blocks (true)
     bool keys_resident = false;
 };
@@ -554,7 +554,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
             size_t off = head;
             int32_t max_nb = 0, max_cap = 0, max_z = 0, max_sum = 0;
             const bool use_sum = tune.summary == 1 || (tune.summary == 0 && n >= kSumSamplesPerCu * dev.cus);
-            const int32_t keys_grid = tune.keys_resident ? nz::keys_resident_wgs() * dev.cus : 0;
+            const int32_t keys_grid = tune.keys_resident ? (nz::keys_resident_wgs() + 1) / 2 * dev.cus : 0;
             uint32_t max_N = 0;
             int64_t max_site = 0;
             std::vector<int32_t> desc_of_chunk(n);
@@ -1000,8 +1000,10 @@ int run_split(SplitPlan &sp, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_
     // Side by side, each group's keys launch keeps the CU slots it is given:
     // with a workgroup per block of sites, the short keys workgroups would hand
     // their slots one by one to the other group's long-lived labelling and
-    // sweep workgroups (L = 16 learned step: 46.5 -> 43.0 ms; a batch that
-    // runs as one group is faster with a workgroup per block).
+    // sweep workgroups (L = 16 learned step: 46.5 -> 43.0 ms with all the
+    // slots a CU holds, 42.7 ms with half of them, which leaves the other
+    // group's labelling room; a batch that runs as one group is faster with a
+    // workgroup per block).
     Tune ts = tune;
     ts.keys_resident = true;
     // the second group starts after the work already queued on the caller's stream
