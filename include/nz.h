@@ -201,7 +201,7 @@ int nz_batch_workspace_bytes(const nz_job *jobs, int32_t njobs, const nz_tuning 
  *   tune           may be NULL;  stream  hipStream_t (NULL: default stream).
  * Returns after the results are in d_nstar / d_mass (the call synchronises the
  * stream, because samples whose key band or bucket ran short are redone).
- * A batch with at least 512 samples of narrow neighbourhoods (z <= 64) and 512
+ * A batch with at least 256 samples of narrow neighbourhoods (z <= 64) and 256
  * of wider ones runs the two groups side by side when the workspace holds both
  * resident (nz_batch_workspace_bytes sizes it so): the wider group on a second
  * host thread and a library-owned stream that first waits for the work already

@@ -934,7 +934,10 @@ NZ_API int nz_last_batch_timing(double ms[6])
 // second host thread and stream), so that one group's sweep overlaps the
 // other's keys and labelling.  Each group gets its own share of the workspace.
 
-constexpr int64_t kSplitMinSamples = 512;
+// (256 rather than 512: the L = 24 table of 27 masks x 200 has 400 narrow
+// samples, and split it runs 163-167 ms instead of 170-174 learned, 333 ms
+// instead of 345-404 plain)
+constexpr int64_t kSplitMinSamples = 256;
 // widest neighbourhood of the first group (L = 16, 7 compact masks x 1000,
 // learned: 47.0 ms with z <= 64, 47.5 with z <= 130, 49.9 with z <= 220;
 // with the keys launches keeping their slots: 43.0 ms with z <= 64, 44.1 with

@@ -147,7 +147,24 @@ def test_workspace_covers_two_groups(monkeypatch):
     monkeypatch.setenv("NZ_DEBUG_NO_SPLIT", "1")
     one = nz.nz_batch_workspace_bytes(jobs)
     assert both > one
-    # too few wide samples: one group
-    small = jobs[:3] + [dict(jobs[3], nsamples=100)]
     monkeypatch.delenv("NZ_DEBUG_NO_SPLIT")
-    assert nz.nz_batch_workspace_bytes(small) < nz.nz_batch_workspace_bytes(jobs)
+    assert nz.nz_batch_workspace_bytes(jobs[:3] + [dict(jobs[3], nsamples=100)]) < both
+
+
+def test_split_needs_256_samples_in_each_group(monkeypatch):
+    """Two groups only when both hold at least 256 samples; otherwise the
+    workspace is the one-group size."""
+    def sizes(n_narrow, n_wide):
+        jobs = [dict(L=12, zone_mask=0x01, seed=1, nsamples=n_narrow, n0=-1),
+                dict(L=12, zone_mask=0x7F, seed=2, nsamples=n_wide, n0=-1)]
+        monkeypatch.delenv("NZ_DEBUG_NO_SPLIT", raising=False)
+        split = nz.nz_batch_workspace_bytes(jobs)
+        monkeypatch.setenv("NZ_DEBUG_NO_SPLIT", "1")
+        one = nz.nz_batch_workspace_bytes(jobs)
+        return split, one
+    s, o = sizes(256, 256)
+    assert s > o
+    s, o = sizes(255, 4000)
+    assert s == o
+    s, o = sizes(4000, 255)
+    assert s == o
