@@ -2031,9 +2031,13 @@ int32_t keys_sites_per_block() { return KEYS_SITES_PER_BLOCK; }
 
 int32_t keys_resident_wgs()
 {
-    int n = 0;
-    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, nz_keys_kernel, KEYS_THREADS, 0) != hipSuccess || n < 1) n = 1;
-    return n;
+    // one kernel, one architecture: the answer is fixed for the process
+    static const int32_t wgs = [] {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, nz_keys_kernel, KEYS_THREADS, 0) != hipSuccess || n < 1) n = 1;
+        return static_cast<int32_t>(n);
+    }();
+    return wgs;
 }
 
 hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int32_t max_cap, uint8_t *ws,
