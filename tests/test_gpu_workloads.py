@@ -24,19 +24,19 @@ def random_masks(count=20, seed=0x24):
     return sorted(int(m) for m in rng.choice(pool, size=count, replace=False))
 
 
-def _run(jobs, ws_cap_gb=None):
+def _run(jobs, ws_cap_gb=None, tune=None):
     import torch
 
     from paper_2607_18991_amd import nz
 
     total = sum(j["nsamples"] for j in jobs)
-    need = nz.nz_batch_workspace_bytes(jobs)
+    need = nz.nz_batch_workspace_bytes(jobs, tune)
     if ws_cap_gb is not None:
         need = min(need, int(ws_cap_gb * 2**30))
     ws = torch.empty(need, dtype=torch.uint8, device="cuda")
     dn = torch.empty(total, dtype=torch.int32, device="cuda")
     dm = torch.empty(total, dtype=torch.int32, device="cuda")
-    nz.nz_sweep_batch(jobs, ws, dn, dm)
+    nz.nz_sweep_batch(jobs, ws, dn, dm, tune=tune)
     torch.cuda.synchronize()
     out = dn.cpu().numpy(), dm.cpu().numpy()
     del ws
@@ -67,6 +67,24 @@ def _learned_and_plain(jobs, ws_cap_gb=None):
     pn, pm = _run(learned.plan_band_only(model, jobs), ws_cap_gb)
     assert (ln == pn).all() and (lm == pm).all(), "learned prefill changed an output"
     return ln, lm
+
+
+def test_bench_batch_L16_compact_as_timed():
+    """The benchmark's own batch (L = 16, the 7 compact masks x 1000, its
+    seed) in the launch configuration it times: learned and plain plans, each
+    with its tuned batch entry, narrow and wide neighbourhoods as two groups
+    side by side.  Learned equals plain sample by sample; the oracle checks
+    the first and the last sample of every mask."""
+    from paper_2607_18991_amd import autotune, learned
+
+    jobs = [dict(L=16, zone_mask=m, seed=0x5EED1016, nsamples=1000) for m in COMPACT]
+    model = learned.PrefillModel.load()
+    jl, jp = model.plan(jobs), learned.plan_band_only(model, jobs)
+    ln, lm = _run(jl, tune=autotune.for_jobs(jl) or None)
+    pn, pm = _run(jp, tune=autotune.for_jobs(jp) or None)
+    assert (ln == pn).all() and (lm == pm).all(), "learned prefill changed an output"
+    _check_oracle(jobs, ln, lm, lambda j: [(0, 1), (999, 1)])
+    assert (ln > 0).all()
 
 
 def test_W2_L8_compact_1e4():
