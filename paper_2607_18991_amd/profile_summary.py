@@ -9,8 +9,9 @@ bench.py reports that traffic only while those sources are unchanged.
 
 Counter scaling: FETCH_SIZE and WRITE_SIZE are KiB per dispatch; a plain
 device copy of 1 GiB reads FETCH_SIZE = 0.5 GiB and WRITE_SIZE = 1 GiB on
-this chip, so fetched bytes are FETCH_SIZE * 1024 * FETCH_SCALE and written
-bytes WRITE_SIZE * 1024 * WRITE_SCALE.
+this chip (copy_calibration.py measures it), so fetched bytes are
+FETCH_SIZE * 1024 * FETCH_SCALE and written bytes WRITE_SIZE * 1024 *
+WRITE_SCALE.
 """
 from __future__ import annotations
 
