@@ -40,7 +40,7 @@ def summarize(fetch_dir: str, write_dir: str, commands: str, out: str):
     fetch = counters(fetch_dir, "FETCH_SIZE")
     write = counters(write_dir, "WRITE_SIZE")
     lines = ["# Traffic counter calibration: a 1 GiB device copy", "",
-             "Commands (GPU box, from the repository root):", "", "```"]
+             "Commands (on an MI355X, from the repository root):", "", "```"]
     lines += open(commands).read().strip().splitlines()
     lines += ["```", "", f"Each dispatch of the copy reads {BYTES} bytes and writes {BYTES} bytes.", "",
               "| kernel | dispatches | FETCH_SIZE bytes / dispatch | read / FETCH | WRITE_SIZE bytes / dispatch | "

@@ -87,7 +87,7 @@ def main():
     stats = kernel_stats(args.stats)
     fetch = counters(args.fetch, "FETCH_SIZE")
     write = counters(args.write, "WRITE_SIZE")
-    lines = [f"# {args.title}", "", "Commands (GPU box, from the repository root):", "", "```"]
+    lines = [f"# {args.title}", "", "Commands (on an MI355X, from the repository root):", "", "```"]
     lines += open(args.commands).read().strip().splitlines()
     lines += ["```", "", f"Kernel time ({args.steps} bench steps in the trace run):", "",
               "| kernel | calls | total ms | average ms | % |", "|---|---|---|---|---|"]
