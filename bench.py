@@ -94,6 +94,22 @@ def summarise(res, steps, S, z):
         alg_bytes += serial * share[k] * bytes_per_addition(z[m])
     launches = max(res["phase"]["sweep_launches"], 1)
     sweep_ms = res["phase"]["sweep_ms"] / launches
+    # neighbour checks: z per sequential addition (the sweep), z/2 per prefilled
+    # site (the hook's half of the offset table); the library counts additions
+    # and prefilled sites per batch, which are split over the masks by each
+    # mask's n* - n0 and n0
+    prefilled = res["stats"]["prefilled_sites"] / steps
+    ser_w = np.zeros(len(masks))
+    pre_w = np.zeros(len(masks))
+    for k, j in enumerate(res["jobs"]):
+        n0 = max(0, int(j.get("n0", 0) or 0))
+        ns = res["ns"][k * S:(k + 1) * S].astype(np.float64)
+        ser_w[k] = np.clip(ns - n0, 0, None).sum()
+        pre_w[k] = n0 * S
+    zs = np.array([z[m] for m in masks], dtype=np.float64)
+    checks_sweep = serial * float((ser_w / max(ser_w.sum(), 1.0) * zs).sum())
+    checks_pre = prefilled * float((pre_w / max(pre_w.sum(), 1.0) * np.floor(zs / 2)).sum()) if pre_w.sum() else 0.0
+    ph = res["phase"]
     return {
         "ms_per_step": ms_step,
         "site_additions_per_s": adds / (ms_step / 1e3),
@@ -104,6 +120,12 @@ def summarise(res, steps, S, z):
         "phase_ms_per_step": {k: v / steps for k, v in res["phase"].items() if k != "sweep_launches"},
         "sweep_kernel_ms": sweep_ms,
         "sweep_alg_bytes": alg_bytes,
+        "neighbour_checks_per_step": {"sweep": checks_sweep, "prefill": checks_pre},
+        "neighbour_checks_per_s": (checks_sweep + checks_pre) / (ms_step / 1e3),
+        # per phase, over that phase's kernel time summed over the groups
+        "neighbour_checks_per_s_in_phase": {
+            "sweep": checks_sweep / (ph["sweep_ms"] / steps / 1e3) if ph["sweep_ms"] > 0 else None,
+            "prefill": checks_pre / (ph["cc_ms"] / steps / 1e3) if ph["cc_ms"] > 0 and checks_pre else None},
         "tuning": res["tune"],
     }
 
@@ -231,6 +253,7 @@ def main():
                                f"spanning along axis 0, learned prefill + persistent sweep",
                    "L": L, "samples_per_mask": S},
         "samples_per_s": sl["samples_per_s"],
+        "neighbour_checks_per_s": sl["neighbour_checks_per_s"],
         "speedup_learned_vs_plain": sp["ms_per_step"] / sl["ms_per_step"],
         "outputs_identical_plain_vs_learned": identical,
         "learned": sl,
