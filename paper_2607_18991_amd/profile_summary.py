@@ -77,7 +77,8 @@ def main():
     ap.add_argument("--write", required=True, help="output folder of the --pmc WRITE_SIZE run")
     ap.add_argument("--name", required=True)
     ap.add_argument("--title", required=True)
-    ap.add_argument("--commands", required=True, help="text file with the three commands")
+    ap.add_argument("--commands", required=True, help="text file with the commands")
+    ap.add_argument("--l2", default=None, help="output folder of a --pmc TCC_HIT_sum TCC_MISS_sum run (optional)")
     ap.add_argument("--steps", type=int, default=2, help="bench steps in the stats run (warm-up included)")
     ap.add_argument("--sweep", default="nz::nz_sweep_kernel")
     ap.add_argument("--keys", default="nz::nz_keys_kernel")
@@ -103,6 +104,17 @@ def main():
         if f_gb + w_gb < 1e-3:
             continue
         lines.append(f"| `{k}` | {n} | {f_gb:.2f} | {w_gb:.2f} |")
+    if args.l2:
+        hit = counters(args.l2, "TCC_HIT_sum")
+        miss = counters(args.l2, "TCC_MISS_sum")
+        lines += ["", "L2 (one step; TCC_HIT_sum and TCC_MISS_sum, requests summed over the dispatches):", "",
+                  "| kernel | dispatches | L2 requests (M) | hit rate |", "|---|---|---|---|"]
+        for k in sorted(set(hit) | set(miss), key=lambda k: -(hit.get(k, [0, 0])[1] + miss.get(k, [0, 0])[1])):
+            h, mi = hit.get(k, [0, 0.0])[1], miss.get(k, [0, 0.0])[1]
+            if h + mi < 1e5:
+                continue
+            n = max(hit.get(k, [0, 0])[0], miss.get(k, [0, 0])[0])
+            lines.append(f"| `{k}` | {n} | {(h + mi) / 1e6:.1f} | {h / (h + mi):.3f} |")
     sweep_f = sum(v[1] for k, v in fetch.items() if k.startswith(args.sweep)) * 1024 * FETCH_SCALE
     sweep_w = sum(v[1] for k, v in write.items() if k.startswith(args.sweep)) * 1024 * WRITE_SCALE
     launches = max(1, sum(v[0] for k, v in fetch.items() if k.startswith(args.sweep)))
