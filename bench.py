@@ -219,6 +219,7 @@ def main():
     achieved = sl["sweep_alg_bytes"] / (sweep_ms_step / 1e3) / 1e9
     traffic = None
     keys_traffic = None
+    keys_dispatches = None   # per step, from the kernel trace of these sources (redo rounds included)
     rec_path = os.path.join(ROOT, "profiles", "nz_sweep_L16_compact_x1000_learned.json")
     if L == 16 and S == 1000 and os.path.exists(rec_path):
         from paper_2607_18991_amd import profile_summary
@@ -228,6 +229,7 @@ def main():
             traffic = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
             if "keys" in rec:
                 keys_traffic = rec["keys"]["fetch_bytes_per_step"] + rec["keys"]["write_bytes_per_step"]
+                keys_dispatches = rec["keys"].get("dispatches") or None
     # the keys kernel: integer VALU work of Philox4x32-10 (one block of 10
     # rounds, each two 32x32->64 products and four XORs, serves two sites) plus
     # four operations of classification per site, against 256 CUs x 64 lanes x
@@ -263,8 +265,11 @@ def main():
                            "kernel_ms": kernel_ms, "launches_per_step": launches,
                            "alg_bytes_per_launch": sl["sweep_alg_bytes"] / launches},
         "roofline_keys": {"bound": "alu", "achieved": keys_achieved, "peak": alu_peak, "unit": "Tops/s",
-                          "frac": keys_achieved / alu_peak, "traffic": keys_traffic, "kernel": "nz_keys_kernel",
-                          "kernel_ms": sl["phase_ms_per_step"]["keys_ms"] / launches, "launches_per_step": launches,
+                          "frac": keys_achieved / alu_peak,
+                          "traffic": keys_traffic / (keys_dispatches or launches) if keys_traffic else None,
+                          "kernel": "nz_keys_kernel",
+                          "kernel_ms": sl["phase_ms_per_step"]["keys_ms"] / (keys_dispatches or launches),
+                          "launches_per_step": keys_dispatches or launches,
                           "ops_per_site": keys_ops_per_site},
     }
     # "roofline" is the kernel that takes the larger share of the step (a batch
