@@ -279,11 +279,11 @@ def main():
                            else out["roofline_sweep"])
     if args.l24_samples > 0:
         # the same comparison at L = 24 (7,962,624 sites): the 7 compact and 20
-        # random neighbourhoods, one timed step per mode
+        # random neighbourhoods, one untimed and one timed step per mode
         j24 = base_jobs(24, args.l24_samples, masks24)
         jp24, jl24 = learned.plan_band_only(model, j24), model.plan(j24)
-        p24 = run_mode(nz, torch, lambda: learned.plan_band_only(model, j24), 1, 0, autotune.for_jobs(jp24) or None)
-        l24 = run_mode(nz, torch, lambda: model.plan(j24), 1, 0, autotune.for_jobs(jl24) or None)
+        p24 = run_mode(nz, torch, lambda: learned.plan_band_only(model, j24), 1, 1, autotune.for_jobs(jp24) or None)
+        l24 = run_mode(nz, torch, lambda: model.plan(j24), 1, 1, autotune.for_jobs(jl24) or None)
         s24p, s24l = summarise(p24, 1, args.l24_samples, z), summarise(l24, 1, args.l24_samples, z)
         out["L24"] = {"samples_per_mask": args.l24_samples, "masks": masks24,
                       "outputs_identical_plain_vs_learned": bool((p24["ns"] == l24["ns"]).all() and

@@ -66,6 +66,15 @@ class PrefillModel:
         self.size_std = float(size_std)
         self.meta = meta or {}
 
+    @property
+    def params(self) -> np.ndarray:
+        return self._params
+
+    @params.setter
+    def params(self, value) -> None:
+        self._params = np.asarray(value, dtype=np.float32)
+        self._dev_params = {}   # device -> these weights in bf16 on it, uploaded at the first prediction
+
     # ---------------------------------------------------------------- io
     def save(self, path: str = DEFAULT_PATH) -> None:
         with open(path, "w") as f:
@@ -90,7 +99,11 @@ class PrefillModel:
         import torch
 
         x = torch.from_numpy(self.features(masks, Ls)).cuda()
-        pb = torch.from_numpy(to_bf16_bits(self.params).view(np.int16)).cuda()
+        dev = torch.cuda.current_device()
+        pb = self._dev_params.get(dev)
+        if pb is None:
+            pb = torch.from_numpy(to_bf16_bits(self.params).view(np.int16)).cuda()
+            self._dev_params[dev] = pb
         B = x.shape[0]
         y = torch.empty((B, OUT), dtype=torch.float32, device="cuda")
         act = torch.empty((B, nz.NZ_MLP_NACT), dtype=torch.float32, device="cuda")
