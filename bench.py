@@ -153,6 +153,7 @@ def main():
     ap.add_argument("--L", type=int, default=16)
     ap.add_argument("--samples", type=int, default=1000)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--no-per-mask", action="store_true", help="skip the table of each compact mask on its own")
     ap.add_argument("--l24-samples", type=int, default=200, help="samples per mask of the L=24 table (0: skip)")
     ap.add_argument("--mode", choices=["both", "learned", "plain"], default="both",
                     help="profiling aid: run only one path (the JSON line then reports that path)")
@@ -277,6 +278,23 @@ def main():
     # each kernel per group; rates are per launch over its own duration)
     out["roofline"] = dict(out["roofline_keys"] if sl["phase_ms_per_step"]["keys_ms"] > sweep_ms_step
                            else out["roofline_sweep"])
+    if not args.no_per_mask and args.mode == "both":
+        # each compact neighbourhood as a batch of its own (the headline mask is
+        # zones 1-7, 0x7F): learned and plain, one untimed and two timed steps
+        per = {}
+        for m in COMPACT:
+            jm = base_jobs(L, S, [m])
+            jlm, jpm = model.plan(jm), learned.plan_band_only(model, jm)
+            pm_ = run_mode(nz, torch, lambda: learned.plan_band_only(model, jm), 2, 1, autotune.for_jobs(jpm) or None)
+            lm_ = run_mode(nz, torch, lambda: model.plan(jm), 2, 1, autotune.for_jobs(jlm) or None)
+            a, b = summarise(pm_, 2, S, z), summarise(lm_, 2, S, z)
+            per[f"{m:#04x}"] = {"z": z[m], "learned_ms": b["ms_per_step"], "plain_ms": a["ms_per_step"],
+                                "site_additions_per_s": b["site_additions_per_s"], "samples_per_s": b["samples_per_s"],
+                                "speedup_learned_vs_plain": a["ms_per_step"] / b["ms_per_step"],
+                                "outputs_identical_plain_vs_learned": bool((pm_["ns"] == lm_["ns"]).all() and
+                                                                           (pm_["ms"] == lm_["ms"]).all())}
+        out["per_mask"] = per
+        out["headline_mask"] = "0x7f"
     if args.l24_samples > 0:
         # the same comparison at L = 24 (7,962,624 sites): the 7 compact and 20
         # random neighbourhoods, one untimed and one timed step per mode
