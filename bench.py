@@ -278,22 +278,25 @@ def main():
     # each kernel per group; rates are per launch over its own duration)
     out["roofline"] = dict(out["roofline_keys"] if sl["phase_ms_per_step"]["keys_ms"] > sweep_ms_step
                            else out["roofline_sweep"])
-    if not args.no_per_mask and args.mode == "both":
+    def per_mask(Lm, Sm):
         # each compact neighbourhood as a batch of its own (the headline mask is
         # zones 1-7, 0x7F): learned and plain, one untimed and two timed steps
         per = {}
         for m in COMPACT:
-            jm = base_jobs(L, S, [m])
+            jm = base_jobs(Lm, Sm, [m])
             jlm, jpm = model.plan(jm), learned.plan_band_only(model, jm)
             pm_ = run_mode(nz, torch, lambda: learned.plan_band_only(model, jm), 2, 1, autotune.for_jobs(jpm) or None)
             lm_ = run_mode(nz, torch, lambda: model.plan(jm), 2, 1, autotune.for_jobs(jlm) or None)
-            a, b = summarise(pm_, 2, S, z), summarise(lm_, 2, S, z)
+            a, b = summarise(pm_, 2, Sm, z), summarise(lm_, 2, Sm, z)
             per[f"{m:#04x}"] = {"z": z[m], "learned_ms": b["ms_per_step"], "plain_ms": a["ms_per_step"],
                                 "site_additions_per_s": b["site_additions_per_s"], "samples_per_s": b["samples_per_s"],
                                 "speedup_learned_vs_plain": a["ms_per_step"] / b["ms_per_step"],
                                 "outputs_identical_plain_vs_learned": bool((pm_["ns"] == lm_["ns"]).all() and
                                                                            (pm_["ms"] == lm_["ms"]).all())}
-        out["per_mask"] = per
+        return per
+
+    if not args.no_per_mask and args.mode == "both":
+        out["per_mask"] = per_mask(L, S)
         out["headline_mask"] = "0x7f"
     if args.l24_samples > 0:
         # the same comparison at L = 24 (7,962,624 sites): the 7 compact and 20
@@ -304,6 +307,7 @@ def main():
         l24 = run_mode(nz, torch, lambda: model.plan(j24), 1, 1, autotune.for_jobs(jl24) or None)
         s24p, s24l = summarise(p24, 1, args.l24_samples, z), summarise(l24, 1, args.l24_samples, z)
         out["L24"] = {"samples_per_mask": args.l24_samples, "masks": masks24,
+                      "per_mask": per_mask(24, args.l24_samples) if not args.no_per_mask else None,
                       "outputs_identical_plain_vs_learned": bool((p24["ns"] == l24["ns"]).all() and
                                                                  (p24["ms"] == l24["ms"]).all()),
                       "speedup_learned_vs_plain": s24p["ms_per_step"] / s24l["ms_per_step"],
