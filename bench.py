@@ -312,6 +312,15 @@ def main():
                                                                  (p24["ms"] == l24["ms"]).all()),
                       "speedup_learned_vs_plain": s24p["ms_per_step"] / s24l["ms_per_step"],
                       "learned": s24l, "plain": s24p}
+        # the learned sweep against HBM at L = 24, as at L = 16 (rate per launch
+        # over the launches' own durations)
+        l24_launches = max(1.0, float(l24["phase"]["sweep_launches"]))
+        l24_sweep_ms = s24l["phase_ms_per_step"]["sweep_ms"]
+        ach24 = s24l["sweep_alg_bytes"] / (l24_sweep_ms / 1e3) / 1e9 if l24_sweep_ms > 0 else 0.0
+        out["L24"]["roofline_sweep"] = {"bound": "hbm", "achieved": ach24, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                        "frac": ach24 / HBM_PEAK_GBS, "kernel": "nz_sweep_kernel",
+                                        "kernel_ms": l24_sweep_ms / l24_launches,
+                                        "launches_per_step": l24_launches}
     if not args.no_cpu:
         per = 8 if L >= 16 else 32
         cpu_rate, threads, res = cpu_baseline(jobs0, per)
