@@ -162,8 +162,8 @@ def main():
                          "to this path (no benchmark is run)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU; samples are independent and shard by sample "
-                                   "range across GPUs, which is not run here"}), flush=True)
+        print(json.dumps({"error": "the benchmark runs on one GPU; samples are independent and would shard by "
+                                   "sample range across GPUs, which is not run here"}), flush=True)
         sys.exit(2)
 
     import torch
