@@ -193,3 +193,36 @@ def test_shipped_tuning_reproduces_oracle():
             jobs = [dict(L=L, zone_mask=m, seed=515, nsamples=8)]
             gn, gm, _, _ = run_batch(jobs, tune=autotune.lookup(L, m) or None)
             assert_same(jobs, gn, gm, *oracle_batch(jobs))
+
+
+@pytest.mark.parametrize("count", [20, 300])
+def test_zero_sample_job_between_others(count):
+    # 300 samples a side take the two-group path (narrow and wide masks side
+    # by side); outputs stay in job order across the empty job
+    jobs = [dict(L=6, zone_mask=0x01, seed=71, nsamples=count),
+            dict(L=8, zone_mask=0x03, seed=72, nsamples=0),
+            dict(L=6, zone_mask=0x7F, seed=73, nsamples=count // 2 + 150)]
+    gn, gm, back, _ = run_batch(jobs)
+    assert len(gn) == sum(j["nsamples"] for j in jobs) and len(back) == 3
+    assert back[1] == 0
+    assert_same(jobs, gn, gm, *oracle_batch(jobs))
+
+
+def test_empty_inputs():
+    import torch
+
+    from paper_2607_18991_amd import nz
+
+    ns, ms = nz.nz_sweep(8, 0x01, 0, 5)
+    assert ns.size == 0 and ms.size == 0
+    gn, gm, back, _ = run_batch([])
+    assert gn.size == 0 and back.size == 0
+    # a batch with no samples leaves the outputs as they were
+    jobs = [dict(L=8, zone_mask=0x01, seed=1, nsamples=0), dict(L=6, zone_mask=0x7F, seed=2, nsamples=0)]
+    ws = torch.empty(nz.nz_batch_workspace_bytes(jobs), dtype=torch.uint8, device="cuda")
+    dn = torch.full((4,), -7, dtype=torch.int32, device="cuda")
+    dm = torch.full((4,), -7, dtype=torch.int32, device="cuda")
+    back = nz.nz_sweep_batch(jobs, ws, dn, dm)
+    torch.cuda.synchronize()
+    assert (back == 0).all()
+    assert (dn.cpu() == -7).all() and (dm.cpu() == -7).all()
