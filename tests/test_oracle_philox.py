@@ -1,15 +1,45 @@
 """Pins of the oracle's Philox4x32-10 keys and its sort (not GPU).
 
-No published known-answer vectors are available here, so the pin is agreement
-between two implementations written separately from the SC'11 definition (the
-oracle's C and tests/philox_np.py), plus statistical uniformity of the keys and
-the order's defining invariants checked against NumPy's own lexsort.
+The Philox block is pinned to rocRAND's implementation of the same bijection
+(built on the host from ROCm's header by tests/philox_rocrand_ref.hip) and to
+a second implementation written for the tests from the SC'11 definition
+(tests/philox_np.py); the keys' uniformity is tested statistically and the
+order's defining invariants are checked against NumPy's own lexsort.
 """
+import os
+import shutil
+import subprocess
+
 import numpy as np
 import pytest
 from scipy import stats
 
 import philox_np
+
+_ROCM = os.environ.get("ROCM_PATH", "/opt/rocm")
+_ROCRAND_HEADER = os.path.join(_ROCM, "include", "rocrand", "rocrand_philox4x32_10.h")
+
+
+def _hipcc():
+    return shutil.which("hipcc") or (os.path.join(_ROCM, "bin", "hipcc")
+                                     if os.path.exists(os.path.join(_ROCM, "bin", "hipcc")) else None)
+
+
+@pytest.mark.skipif(_hipcc() is None or not os.path.exists(_ROCRAND_HEADER), reason="hipcc or rocRAND missing")
+def test_philox_block_matches_rocrand(nzo, tmp_path):
+    exe = str(tmp_path / "philox_ref")
+    src = os.path.join(os.path.dirname(os.path.abspath(__file__)), "philox_rocrand_ref.hip")
+    subprocess.run([_hipcc(), "--offload-arch=gfx950", "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+                    "-O1", src, "-o", exe], check=True, capture_output=True, timeout=300)
+    rng = np.random.default_rng(7)
+    blocks = [np.zeros(6, dtype=np.uint64), np.full(6, 2**32 - 1, dtype=np.uint64)]
+    blocks += [rng.integers(0, 2**32, size=6, dtype=np.uint64) for _ in range(500)]
+    text = "".join(" ".join(f"{int(w):x}" for w in b) + "\n" for b in blocks)
+    out = subprocess.run([exe], input=text, check=True, capture_output=True, text=True, timeout=60).stdout.split()
+    want = np.array([int(w, 16) for w in out], dtype=np.uint64).reshape(len(blocks), 4)
+    for b, w in zip(blocks, want):
+        got = nzo.philox4x32_10(b[:4].astype(np.uint32), b[4:].astype(np.uint32))
+        assert [int(x) for x in got] == [int(x) for x in w], b
 
 
 def test_philox_block_matches_independent_numpy(nzo):
