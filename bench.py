@@ -130,10 +130,15 @@ def summarise(res, steps, S, z):
     }
 
 
+def cpu_threads():
+    # a one-GPU host share is 16 cores
+    return max(1, min(os.cpu_count() or 1, 16))
+
+
 def cpu_baseline(jobs, per_mask):
     import oracle
 
-    threads = max(1, min(os.cpu_count() or 1, 64))
+    threads = cpu_threads()
     adds = 0
     res = {}
     t0 = time.perf_counter()
@@ -322,13 +327,15 @@ def main():
                                         "kernel_ms": l24_sweep_ms / l24_launches,
                                         "launches_per_step": l24_launches}
     if not args.no_cpu:
-        per = 8 if L >= 16 else 32
+        # every thread takes the same number of samples of each mask (about
+        # 10 s on 16 host cores at L = 16)
+        per = min(S, cpu_threads() * (8 if L >= 16 else 32))
         cpu_rate, threads, res = cpu_baseline(jobs0, per)
         parity = all((res[m][0] == learn["ns"][k * S:k * S + per]).all() and
                      (res[m][1] == learn["ms"][k * S:k * S + per]).all() for k, m in enumerate(COMPACT))
         out["cpu_baseline"] = {"value": cpu_rate, "unit": "site additions/s", "cores": threads, "kind": "oracle",
-                               "sample": f"samples 0..{per - 1} of each of the 7 masks at L={L}, one sample per "
-                                         f"thread (keys, full sort, serial union-find)"}
+                               "sample": f"samples 0..{per - 1} of each of the 7 masks at L={L}, spread over "
+                                         f"{threads} threads (keys, full sort, serial union-find)"}
         out["parity_on_cpu_sample"] = bool(parity)
     print(json.dumps(out), flush=True)
 
