@@ -131,7 +131,7 @@ def summarise(res, steps, S, z):
 
 
 def cpu_threads():
-    # a one-GPU host share is 16 cores
+    # the oracle runs on at most 16 host threads
     return max(1, min(os.cpu_count() or 1, 16))
 
 
