@@ -13,7 +13,8 @@ values quoted in Sec. II.A.1.
     python -m paper_2607_18991_amd.fss --mask 1 --df 0.14079633 --L 16 20 24 28 32 --samples 2000 2000 1000 1000 1000
 
 The second form fits the fractal dimension of the incipient cluster,
-<S_max(p_c)> ~ L^d_f, at a given threshold (the paper's Sec. III.B estimator).
+<S_max(p_c)> ~ L^d_f, at a given threshold (the estimator of Sec. II.A.3,
+eq. (9), whose results are Table II of Sec. III.C).
 """
 from __future__ import annotations
 
@@ -99,7 +100,7 @@ def smax_at(L: int, mask: int, p: float, samples: int, seed: int, boundary: int 
 
 
 def df_estimate(mask: int, p_c: float, Ls, samples, seed: int = 0xDF5, boundary: int = nz.NZ_FREE):
-    """Fractal dimension of the incipient cluster (Sec. II.A.4, Sec. III.B):
+    """Fractal dimension of the incipient cluster (Sec. II.A.3, eq. (9); Sec. III.C, Table II):
     the least-squares slope of ln <S_max(p_c)> against ln L, with its standard
     error from the fit residuals."""
     pts, runs = [], []

@@ -1,5 +1,5 @@
 """The threshold and fractal-dimension estimators end to end on the GPU
-(Sec. II.A.1 eqs. (5)-(6), Sec. III.B eq. (9)).
+(Sec. II.A.1 eqs. (5)-(6); Sec. II.A.3 eq. (9) with Sec. III.C, Table II).
 
 The windows they consume are checked against the oracle sum by sum in
 test_gpu_smax.py; here the estimates themselves are checked against the values
