@@ -63,7 +63,10 @@ def run_mode(nz, torch, make_jobs, steps, warmup, tune):
     torch.cuda.synchronize()
     nz.nz_set_timing(True)
     phase = {"keys_ms": 0.0, "cc_ms": 0.0, "sort_ms": 0.0, "sweep_ms": 0.0, "total_ms": 0.0, "sweep_launches": 0}
+    cc = {"hook_ms": 0.0, "compress_ms": 0.0, "accum_ms": 0.0, "expand_ms": 0.0, "dispatches": 0}
     stats = {}
+    serial = np.zeros(len(jobs), dtype=np.int64)
+    prefilled = np.zeros(len(jobs), dtype=np.int64)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(steps):
@@ -71,55 +74,64 @@ def run_mode(nz, torch, make_jobs, steps, warmup, tune):
         t = nz.nz_last_batch_timing()
         for k in phase:
             phase[k] += t[k]
+        for k, v in nz.nz_last_batch_cc_timing().items():
+            cc[k] += v
         for k, v in nz.nz_last_batch_stats().items():
             stats[k] = stats.get(k, 0) + v
+        a, b = nz.nz_last_batch_job_stats(len(jobs))
+        serial += a
+        prefilled += b
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     nz.nz_set_timing(False)
     del ws
-    return {"wall": wall, "ns": dn.cpu().numpy(), "ms": dm.cpu().numpy(), "phase": phase, "stats": stats,
-            "jobs": jobs, "tune": tune}
+    return {"wall": wall, "ns": dn.cpu().numpy(), "ms": dm.cpu().numpy(), "phase": phase, "cc": cc, "stats": stats,
+            "serial": serial, "prefilled": prefilled, "jobs": jobs, "tune": tune}
+
+
+def prefill_bytes(n0_sites: float, z: int, N: int, samples: int) -> float:
+    """Algorithmic HBM bytes of the bulk labelling: per labelled site z/8
+    occupancy bits and 16 bytes of hook-and-compress forest traffic, plus 8
+    bytes for the size-and-flag finalisation, and one pass over each prefilled
+    sample's N/8-byte bitset."""
+    return n0_sites * (z / 8.0 + 24.0) + samples * N / 8.0
 
 
 def summarise(res, steps, S, z):
     ms_step = res["wall"] / steps * 1e3
     adds = int(res["ns"].astype(np.int64).sum())
-    serial = res["stats"]["serial_steps"] / steps
-    alg_bytes = 0.0
-    # serial steps per mask are not reported separately; weight by each mask's share of n*
-    masks = [j["zone_mask"] for j in res["jobs"]]
-    share = np.array([res["ns"][k * S:(k + 1) * S].astype(np.float64).sum() for k in range(len(masks))])
-    share = share / share.sum()
-    for k, m in enumerate(masks):
-        alg_bytes += serial * share[k] * bytes_per_addition(z[m])
+    jobs = res["jobs"]
+    masks = [j["zone_mask"] for j in jobs]
+    zs = np.array([z[m] for m in masks], dtype=np.float64)
+    # per job and step: sequential additions and prefilled sites (the
+    # library's own counts over the final runs of every sample)
+    ser = np.asarray(res["serial"], dtype=np.float64) / steps
+    pre = np.asarray(res["prefilled"], dtype=np.float64) / steps
+    serial = float(ser.sum())
+    sweep_bytes = float(sum(ser[k] * bytes_per_addition(z[m]) for k, m in enumerate(masks)))
+    pre_bytes = float(sum(prefill_bytes(pre[k], z[m], int(j["L"]) ** 5, int(j["nsamples"]))
+                          for k, (j, m) in enumerate(zip(jobs, masks)) if int(j.get("n0", -1) or -1) > 0))
     launches = max(res["phase"]["sweep_launches"], 1)
     sweep_ms = res["phase"]["sweep_ms"] / launches
     # neighbour checks: z per sequential addition (the sweep), z/2 per prefilled
-    # site (the hook's half of the offset table); the library counts additions
-    # and prefilled sites per batch, which are split over the masks by each
-    # mask's n* - n0 and n0
-    prefilled = res["stats"]["prefilled_sites"] / steps
-    ser_w = np.zeros(len(masks))
-    pre_w = np.zeros(len(masks))
-    for k, j in enumerate(res["jobs"]):
-        n0 = max(0, int(j.get("n0", 0) or 0))
-        ns = res["ns"][k * S:(k + 1) * S].astype(np.float64)
-        ser_w[k] = np.clip(ns - n0, 0, None).sum()
-        pre_w[k] = n0 * S
-    zs = np.array([z[m] for m in masks], dtype=np.float64)
-    checks_sweep = serial * float((ser_w / max(ser_w.sum(), 1.0) * zs).sum())
-    checks_pre = prefilled * float((pre_w / max(pre_w.sum(), 1.0) * np.floor(zs / 2)).sum()) if pre_w.sum() else 0.0
+    # site (the hook's half of the offset table)
+    checks_sweep = float((ser * zs).sum())
+    checks_pre = float((pre * np.floor(zs / 2)).sum())
     ph = res["phase"]
+    cc = res.get("cc") or {}
     return {
         "ms_per_step": ms_step,
         "site_additions_per_s": adds / (ms_step / 1e3),
         "samples_per_s": len(res["ns"]) / (ms_step / 1e3),
         "sequential_steps_per_step": serial,
-        "prefilled_sites_per_step": res["stats"]["prefilled_sites"] / steps,
+        "prefilled_sites_per_step": float(pre.sum()),
         "backoffs_per_step": res["stats"]["backoffs"] / steps,
-        "phase_ms_per_step": {k: v / steps for k, v in res["phase"].items() if k != "sweep_launches"},
+        "phase_ms_per_step": {k: v / steps for k, v in ph.items() if k != "sweep_launches"},
+        "labelling_ms_per_step": {k: v / steps for k, v in cc.items() if k != "dispatches"},
+        "labelling_dispatches_per_step": cc.get("dispatches", 0) / steps,
         "sweep_kernel_ms": sweep_ms,
-        "sweep_alg_bytes": alg_bytes,
+        "sweep_alg_bytes": sweep_bytes,
+        "prefill_alg_bytes": pre_bytes,
         "neighbour_checks_per_step": {"sweep": checks_sweep, "prefill": checks_pre},
         "neighbour_checks_per_s": (checks_sweep + checks_pre) / (ms_step / 1e3),
         # per phase, over that phase's kernel time summed over the groups
@@ -130,24 +142,140 @@ def summarise(res, steps, S, z):
     }
 
 
+def hbm_roofline(kernel, alg_bytes_step, ms_step, launches, traffic=None):
+    """Algorithmic bytes of a step's launches over their summed duration (HIP
+    events on the launch streams), i.e. bytes per launch over the average
+    launch duration."""
+    achieved = alg_bytes_step / (ms_step / 1e3) / 1e9 if ms_step > 0 else 0.0
+    return {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": kernel,
+            "kernel_ms": ms_step / max(launches, 1e-9), "launches_per_step": launches,
+            "alg_bytes_per_launch": alg_bytes_step / max(launches, 1e-9)}
+
+
+def profile_record(name):
+    """Per-kernel HBM traffic of one step from the committed counter runs
+    (profiles/<name>.json), if they were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", name + ".json")
+    if not os.path.exists(path):
+        return None
+    from paper_2607_18991_amd import profile_summary
+
+    rec = json.load(open(path))
+    if rec.get("source_sha1") != profile_summary.source_sha1() or "kernels" not in rec:
+        return None
+    return rec
+
+
+def traffic_of(prof, prefixes):
+    """(HBM bytes per step, dispatches per step) of the kernels whose names
+    start with any of prefixes, from a profile record."""
+    if not prof:
+        return None, None
+    b = n = 0.0
+    steps = prof.get("steps", 1)
+    for k, v in prof["kernels"].items():
+        if any(k.startswith(p) for p in prefixes):
+            b += v["fetch_bytes"] + v["write_bytes"]
+            n += v["dispatches"]
+    return (b / steps if n else None), (n / steps or None)
+
+
+def rooflines(summ, res, steps, N, prof):
+    """HBM rooflines of the bulk labelling and the sweep, the integer-ALU
+    roofline of the keys kernel, and "roofline" = the phase with the largest
+    kernel time per step."""
+    ph = summ["phase_ms_per_step"]
+    sweep_launches = res["phase"]["sweep_launches"] / steps
+    out = {}
+    t, _ = traffic_of(prof, ["nz::nz_sweep_kernel"])
+    out["roofline_sweep"] = hbm_roofline("nz_sweep_kernel", summ["sweep_alg_bytes"], ph["sweep_ms"],
+                                         max(sweep_launches, 1.0), t / max(sweep_launches, 1.0) if t else None)
+    lab = summ["labelling_ms_per_step"]
+    nlab = summ["labelling_dispatches_per_step"]
+    if summ["prefill_alg_bytes"] > 0 and nlab > 0:
+        lab_ms = sum(lab.values())
+        t, _ = traffic_of(prof, ["nz::nz_hook_kernel", "nz::nz_compress_kernel", "nz::nz_accum_kernel",
+                                 "nz::nz_expand_kernel"])
+        r = hbm_roofline("bulk labelling (nz_hook_kernel, nz_compress_kernel, nz_accum_kernel, nz_expand_kernel)",
+                         summ["prefill_alg_bytes"], lab_ms, nlab, t / nlab if t else None)
+        r["kernel_ms_split"] = {k: v / nlab for k, v in lab.items()}
+        out["roofline_prefill"] = r
+    keys = keys_roofline(N * len(res["ns"]), ph["keys_ms"], prof)
+    out["roofline_keys"] = keys
+    share = {"roofline_sweep": ph["sweep_ms"], "roofline_keys": ph["keys_ms"],
+             "roofline_prefill": sum(lab.values()) if "roofline_prefill" in out else 0.0}
+    out["roofline"] = dict(out[max(share, key=share.get)])
+    out["roofline_share_ms_per_step"] = share
+    return out
+
+
+def keys_roofline(sites_step, keys_ms_step, prof):
+    """Keys kernel: sites keyed per second against the chip's measured rate of
+    the Philox4x32-10 arithmetic alone (profiles/alu_peak.json: ten rounds of
+    two v_mad_u64_u32 and two v_bitop3_b32 per block of two sites, timed on
+    every CU), or, without that file, 256 CUs x 64 lanes x 2.4 GHz over 34
+    integer operations per site."""
+    achieved = sites_step / (keys_ms_step / 1e3) / 1e9 if keys_ms_step > 0 else 0.0
+    peak_path = os.path.join(ROOT, "profiles", "alu_peak.json")
+    if os.path.exists(peak_path):
+        pk = json.load(open(peak_path))
+        peak, basis = pk["philox_sites_per_s"] / 1e9, "measured Philox4x32-10 block rate (profiles/alu_peak.json)"
+    else:
+        peak, basis = 256 * 64 * 2.4e9 / 34 / 1e9, "256 CUs x 64 lanes x 2.4 GHz / 34 operations per site"
+    t, n = traffic_of(prof, ["nz::nz_keys_kernel"])
+    return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gsites/s", "frac": achieved / peak,
+            "traffic": t / n if t else None, "kernel": "nz_keys_kernel", "launches_per_step": n,
+            "kernel_ms": keys_ms_step / n if n else None, "peak_basis": basis}
+
+
+def host_cpu():
+    """The host's CPU: logical CPUs, the ones this process may run on, model
+    name and socket count (from /proc/cpuinfo)."""
+    model, sockets = None, set()
+    try:
+        for line in open("/proc/cpuinfo"):
+            k, _, v = line.partition(":")
+            k = k.strip()
+            if k == "model name" and model is None:
+                model = v.strip()
+            elif k == "physical id":
+                sockets.add(v.strip())
+    except OSError:
+        pass
+    return {"nproc": os.cpu_count(), "affinity": len(os.sched_getaffinity(0)), "model": model,
+            "sockets": len(sockets) or None}
+
+
 def cpu_threads():
-    # the oracle runs on at most 16 host threads
-    return max(1, min(os.cpu_count() or 1, 16))
+    """Host threads for the oracle: every CPU this process may run on, capped by
+    OMP_NUM_THREADS where the host sets it (a GPU host allots a share of its
+    cores to each GPU)."""
+    n = len(os.sched_getaffinity(0))
+    cap = os.environ.get("OMP_NUM_THREADS")
+    if cap and cap.isdigit() and int(cap) > 0:
+        n = min(n, int(cap))
+    return max(1, n)
 
 
-def cpu_baseline(jobs, per_mask):
+def cpu_baseline(jobs, per_mask, threads):
+    """The oracle's own Newman-Ziff (keys, full sort, serial union-find) on
+    samples 0..per_mask-1 of every job, one sample per thread at a time (the
+    paper's ordinary work division); returns additions/s, the results and the
+    keys / sort / sweep thread-seconds."""
     import oracle
 
-    threads = cpu_threads()
     adds = 0
     res = {}
+    split = np.zeros(3)
     t0 = time.perf_counter()
     for j in jobs:
-        ns, ms = oracle.sweep_many(j["L"], j["zone_mask"], j["seed"], 0, per_mask, nthreads=threads)
+        ns, ms, tm = oracle.sweep_many(j["L"], j["zone_mask"], j["seed"], 0, per_mask, nthreads=threads, times=True)
         res[j["zone_mask"]] = (ns, ms)
         adds += int(ns.sum())
+        split += tm
     wall = time.perf_counter() - t0
-    return adds / wall, threads, res
+    return adds / wall, res, {"keys_s": split[0], "sort_s": split[1], "sweep_s": split[2], "wall_s": wall}
 
 
 def main():
@@ -160,6 +288,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-per-mask", action="store_true", help="skip the table of each compact mask on its own")
     ap.add_argument("--l24-samples", type=int, default=200, help="samples per mask of the L=24 table (0: skip)")
+    ap.add_argument("--l24-only", action="store_true",
+                    help="profiling aid: time only the L=24 table (27 masks) in --mode, --steps and --warmup, and "
+                         "print its figures")
     ap.add_argument("--mode", choices=["both", "learned", "plain"], default="both",
                     help="profiling aid: run only one path (the JSON line then reports that path)")
     ap.add_argument("--autotune-out", default=None,
@@ -200,6 +331,22 @@ def main():
         autotune.save_table(table, args.autotune_out)
         return
 
+    if args.l24_only:
+        j24 = base_jobs(24, args.l24_samples, masks24)
+        S24 = args.l24_samples
+        res = {}
+        for mode in (("plain", "learned") if args.mode == "both" else (args.mode,)):
+            mk = (lambda: learned.plan_band_only(model, j24)) if mode == "plain" else (lambda: model.plan(j24))
+            r = run_mode(nz, torch, mk, args.steps, args.warmup, autotune.for_jobs(mk()) or None)
+            res[mode] = (r, summarise(r, args.steps, S24, z))
+        out = {"workload": f"L=24 (N={24**5}) x 27 masks x {S24}", "masks": masks24}
+        for mode, (r, sm) in res.items():
+            out[mode] = sm
+            out[mode].update(rooflines(sm, r, args.steps, 24**5,
+                                       profile_record(f"nz_sweep_L24_27masks_x{S24}_{mode}")))
+        print(json.dumps(out), flush=True)
+        return
+
     if args.mode in ("both", "plain"):
         jp = learned.plan_band_only(model, jobs0)
         plain = run_mode(nz, torch, lambda: learned.plan_band_only(model, jobs0), args.steps, args.warmup,
@@ -216,34 +363,7 @@ def main():
     sp = summarise(plain, args.steps, S, z)
     sl = summarise(learn, args.steps, S, z)
 
-    # the sweep kernel: algorithmic bytes of a step's launches over their time
-    # (HIP events on the launch stream), i.e. per launch over the average
-    # launch duration
-    sweep_ms_step = sl["phase_ms_per_step"]["sweep_ms"]
-    launches = max(1.0, learn["phase"]["sweep_launches"] / args.steps)
-    kernel_ms = sweep_ms_step / launches
-    achieved = sl["sweep_alg_bytes"] / (sweep_ms_step / 1e3) / 1e9
-    traffic = None
-    keys_traffic = None
-    keys_dispatches = None   # per step, from the kernel trace of these sources (redo rounds included)
-    rec_path = os.path.join(ROOT, "profiles", "nz_sweep_L16_compact_x1000_learned.json")
-    if L == 16 and S == 1000 and os.path.exists(rec_path):
-        from paper_2607_18991_amd import profile_summary
-
-        rec = json.load(open(rec_path))
-        if rec.get("source_sha1") == profile_summary.source_sha1():
-            traffic = rec["fetch_bytes_per_launch"] + rec["write_bytes_per_launch"]
-            if "keys" in rec:
-                keys_traffic = rec["keys"]["fetch_bytes_per_step"] + rec["keys"]["write_bytes_per_step"]
-                keys_dispatches = rec["keys"].get("dispatches") or None
-    # the keys kernel: integer VALU work of Philox4x32-10 (one block of 10
-    # rounds, each two 32x32->64 products and four XORs, serves two sites) plus
-    # four operations of classification per site, against 256 CUs x 64 lanes x
-    # 2.4 GHz of 32-bit integer operations
-    keys_ops_per_site = 10 * 6 / 2 + 4
-    keyed_sites = float(N) * len(learn["ns"])
-    keys_achieved = keyed_sites * keys_ops_per_site / (sl["phase_ms_per_step"]["keys_ms"] / 1e3) / 1e12
-    alu_peak = 256 * 64 * 2.4e9 / 1e12
+    prof = profile_record(f"nz_sweep_L{L}_compact_x{S}_learned")
     out = {
         "metric": "site additions/s and samples/s at L=16, zones 1-7; learned-prefill vs plain speedup",
         "value": sl["site_additions_per_s"],
@@ -266,23 +386,8 @@ def main():
         "outputs_identical_plain_vs_learned": identical,
         "learned": sl,
         "plain": sp,
-        "roofline_sweep": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                           "frac": achieved / HBM_PEAK_GBS, "traffic": traffic, "kernel": "nz_sweep_kernel",
-                           "kernel_ms": kernel_ms, "launches_per_step": launches,
-                           "alg_bytes_per_launch": sl["sweep_alg_bytes"] / launches},
-        "roofline_keys": {"bound": "alu", "achieved": keys_achieved, "peak": alu_peak, "unit": "Tops/s",
-                          "frac": keys_achieved / alu_peak,
-                          "traffic": keys_traffic / (keys_dispatches or launches) if keys_traffic else None,
-                          "kernel": "nz_keys_kernel",
-                          "kernel_ms": sl["phase_ms_per_step"]["keys_ms"] / (keys_dispatches or launches),
-                          "launches_per_step": keys_dispatches or launches,
-                          "ops_per_site": keys_ops_per_site},
     }
-    # "roofline" is the kernel that takes the larger share of the step (a batch
-    # whose narrow and wide neighbourhoods run side by side has one launch of
-    # each kernel per group; rates are per launch over its own duration)
-    out["roofline"] = dict(out["roofline_keys"] if sl["phase_ms_per_step"]["keys_ms"] > sweep_ms_step
-                           else out["roofline_sweep"])
+    out.update(rooflines(sl, learn, args.steps, N, prof))
     def per_mask(Lm, Sm):
         # each compact neighbourhood as a batch of its own (the headline mask is
         # zones 1-7, 0x7F): learned and plain, one untimed and two timed steps
@@ -317,25 +422,32 @@ def main():
                                                                  (p24["ms"] == l24["ms"]).all()),
                       "speedup_learned_vs_plain": s24p["ms_per_step"] / s24l["ms_per_step"],
                       "learned": s24l, "plain": s24p}
-        # the learned sweep against HBM at L = 24, as at L = 16 (rate per launch
-        # over the launches' own durations)
-        l24_launches = max(1.0, float(l24["phase"]["sweep_launches"]))
-        l24_sweep_ms = s24l["phase_ms_per_step"]["sweep_ms"]
-        ach24 = s24l["sweep_alg_bytes"] / (l24_sweep_ms / 1e3) / 1e9 if l24_sweep_ms > 0 else 0.0
-        out["L24"]["roofline_sweep"] = {"bound": "hbm", "achieved": ach24, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                        "frac": ach24 / HBM_PEAK_GBS, "kernel": "nz_sweep_kernel",
-                                        "kernel_ms": l24_sweep_ms / l24_launches,
-                                        "launches_per_step": l24_launches}
+        # the learned path's rooflines at L = 24, as at L = 16
+        out["L24"].update(rooflines(s24l, l24, 1, 24**5,
+                                    profile_record(f"nz_sweep_L24_27masks_x{args.l24_samples}_learned")))
     if not args.no_cpu:
-        # every thread takes the same number of samples of each mask (about
-        # 10 s on 16 host cores at L = 16)
-        per = min(S, cpu_threads() * (8 if L >= 16 else 32))
-        cpu_rate, threads, res = cpu_baseline(jobs0, per)
+        # the oracle on the host: all the threads this process may use (every
+        # thread takes the same number of samples of each mask, about 10 s on
+        # 16 host cores at L = 16), then one thread on a subset of them; the
+        # GPU's n* and mass must equal the oracle's on every sample timed
+        threads = cpu_threads()
+        per = min(S, threads * (8 if L >= 16 else 32))
+        cpu_rate, res, split = cpu_baseline(jobs0, per, threads)
+        per1 = min(per, 2 if L >= 16 else 16)
+        one_rate, res1, split1 = cpu_baseline(jobs0, per1, 1)
         parity = all((res[m][0] == learn["ns"][k * S:k * S + per]).all() and
                      (res[m][1] == learn["ms"][k * S:k * S + per]).all() for k, m in enumerate(COMPACT))
+        parity = parity and all((res1[m][0] == learn["ns"][k * S:k * S + per1]).all() for k, m in enumerate(COMPACT))
         out["cpu_baseline"] = {"value": cpu_rate, "unit": "site additions/s", "cores": threads, "kind": "oracle",
-                               "sample": f"samples 0..{per - 1} of each of the 7 masks at L={L}, spread over "
-                                         f"{threads} threads (keys, full sort, serial union-find)"}
+                               "sample": f"samples 0..{per - 1} of each of the 7 masks at L={L}, one sample per "
+                                         f"thread at a time on {threads} threads (keys, full sort, serial "
+                                         f"union-find)",
+                               "host": host_cpu(),
+                               "thread_seconds": split,
+                               "single_core": {"value": one_rate, "unit": "site additions/s", "threads": 1,
+                                               "sample": f"samples 0..{per1 - 1} of each of the 7 masks",
+                                               "thread_seconds": split1},
+                               "samples_per_s": len(COMPACT) * per / split["wall_s"]}
         out["parity_on_cpu_sample"] = bool(parity)
     print(json.dumps(out), flush=True)
 

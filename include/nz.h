@@ -222,6 +222,12 @@ int nz_sweep_batch(const nz_job *jobs, int32_t njobs, void *d_ws, size_t ws_byte
  * final runs of all samples) and sites added by the sequential sweep. */
 int nz_last_batch_stats(int64_t stats[6]);
 
+/* Per job of the last nz_sweep_batch on the calling thread (njobs must be that
+ * batch's job count; HOST arrays, caller's job order): serial[j] = sites added
+ * by the sequential sweep, prefilled[j] = sites occupied by the bulk prefill,
+ * each summed over the final runs of job j's samples. */
+int nz_last_batch_job_stats(int64_t *serial, int64_t *prefilled, int32_t njobs);
+
 /* Phase timing of nz_sweep_batch with HIP events recorded on the caller's
  * stream around each group of launches.  nz_set_timing(1) turns it on for later
  * calls on the calling thread (0 turns it off).  nz_last_batch_timing fills
@@ -229,6 +235,13 @@ int nz_last_batch_stats(int64_t stats[6]);
  * bucket sort, sweep, the whole call, and ms[5] = number of sweep launches. */
 int nz_set_timing(int enable);
 int nz_last_batch_timing(double ms[6]);
+
+/* With timing on, the bulk labelling of free-boundary prefills split by kernel
+ * (HIP events on the launch stream around every dispatch, in-chunk backoff
+ * passes included): ms[0..3] = milliseconds summed over dispatches in the hook,
+ * compress, size-and-flag and expand kernels, ms[4] = number of dispatches of
+ * each. */
+int nz_last_batch_cc_timing(double ms[5]);
 
 /*
  * MLP that predicts the mean and spread of n* / N for the learned prefill: three dense
@@ -261,6 +274,36 @@ int nz_mlp_backward(const uint16_t *params_bf16, const float *x, const float *ac
                     const float *dy, float *grad, int32_t B, void *stream);
 int nz_mlp_adam(float *params_fp32, uint16_t *params_bf16, const float *grad, float *adam_m,
                 float *adam_v, const float hyper[5], int32_t step, void *stream);
+
+/*
+ * Learned-prefill planning (host arithmetic; no device work).
+ *
+ * nz_mlp_size_stats -- mean and standard deviation (population, 1 if zero) of
+ *   the size variable L^(-1/nu), nu = 0.5720, over B lattices of sides L[0..B)
+ *   (HOST); out[0] = mean, out[1] = std: the standardisation of the MLP's size
+ *   input, taken over its training set.
+ * nz_mlp_features -- the MLP's input rows x[B][8] (HOST, written): the seven
+ *   bits of zone_mask[b] (zone k in column k-1) and
+ *   (L[b]^(-1/nu) - size_mean) / size_std.
+ * nz_prefill_target -- the training target of one lattice of side L from the
+ *   n* of its samples (HOST, nsamples entries; samples with n* = 0 never
+ *   span and are left out): out[0] = samples used, out[1] = mean of n* / N,
+ *   out[2] = their population standard deviation, at least 0.5 / N,
+ *   out[3], out[4] = the natural logarithms of out[1], out[2] (the MLP's
+ *   regression targets).  NZ_EINVAL when no sample spans.
+ * nz_prefill_plan -- from the MLP's outputs y[j] = (ln mean, ln std) of n* / N
+ *   for job j (HOST float [njobs][2]), writes into jobs[j] (HOST):
+ *     band_hi = min(N, ceil((mean + band_sigma std) N) + 1024);
+ *     plain != 0: n0 = -1 (a plain sweep that only uses the band);
+ *     else n0 = floor((mean - k_sigma std) N) clamped to [0, N-1] and
+ *          backoff = ceil(k_sigma std N).
+ *   None of these changes any n* or mass (the backoff keeps n* exact).
+ */
+int nz_mlp_size_stats(const int32_t *L, int32_t B, double out[2]);
+int nz_mlp_features(const uint32_t *zone_mask, const int32_t *L, int32_t B, double size_mean, double size_std,
+                    float *x);
+int nz_prefill_target(const int32_t *nstar, int64_t nsamples, int32_t L, double out[5]);
+int nz_prefill_plan(const float *y, nz_job *jobs, int32_t njobs, double k_sigma, double band_sigma, int32_t plain);
 
 /* Weighted mean squared error of y against target over B rows and both outputs,
  * sum_b w_b / sum(w) * sum_o (y - t)^2, into loss[0], and its gradient

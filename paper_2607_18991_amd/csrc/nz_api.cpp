@@ -29,6 +29,32 @@ thread_local std::string g_err = "no error";
 thread_local int64_t g_stats[6] = {0, 0, 0, 0, 0, 0};
 thread_local bool g_timing = false;
 thread_local double g_ms[6] = {0, 0, 0, 0, 0, 0};
+// per job of the last batch (caller's job order): sequential additions and
+// sites occupied by the bulk prefill, summed over the final runs of its samples
+thread_local std::vector<int64_t> g_job_serial, g_job_pre;
+// bulk-labelling kernels of the last batch: milliseconds in hook, compress,
+// size pass, expand (summed over dispatches) and the number of dispatches
+thread_local double g_cc_ms[5] = {0, 0, 0, 0, 0};
+
+// Events around each kernel of the bulk labelling; a chunk launches it up to
+// three times (the first pass and two in-chunk backoffs).
+struct PrefillEvents {
+    hipEvent_t ev[3][5] = {};
+    int used = 0;
+    bool ok = false;
+    PrefillEvents()
+    {
+        ok = true;
+        for (auto &row : ev)
+            for (auto &e : row) ok = ok && hipEventCreate(&e) == hipSuccess;
+    }
+    ~PrefillEvents()
+    {
+        for (auto &row : ev)
+            for (auto &e : row)
+                if (e) (void)hipEventDestroy(e);
+    }
+};
 
 // Events bracketing the phases of one chunk (keys, prefill, sort, sweep).
 struct PhaseEvents {
@@ -464,6 +490,9 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
     if (int rc = device_info(dev)) return rc;
     for (int k = 0; k < 6; ++k) g_stats[k] = 0;
     for (int k = 0; k < 6; ++k) g_ms[k] = 0.0;
+    for (int k = 0; k < 5; ++k) g_cc_ms[k] = 0.0;
+    g_job_serial.assign(static_cast<size_t>(std::max(njobs, 0)), 0);
+    g_job_pre.assign(static_cast<size_t>(std::max(njobs, 0)), 0);
     if (h_backoffs)
         for (int j = 0; j < njobs; ++j) h_backoffs[j] = 0;
 
@@ -644,10 +673,19 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
 
             // ---- launches
             PhaseEvents *pe = nullptr;
+            PrefillEvents *pfe = nullptr;
             if (g_timing) {
                 static thread_local PhaseEvents events;   // released when the thread ends
+                static thread_local PrefillEvents pevents;
                 if (events.ok) pe = &events;
+                if (pevents.ok) {
+                    pfe = &pevents;
+                    pfe->used = 0;
+                }
             }
+            auto prefill_events = [&]() -> hipEvent_t * {
+                return pfe && pfe->used < 3 ? pfe->ev[pfe->used++] : nullptr;
+            };
             if (pe) HIP_TRY(hipEventRecord(pe->ev[0], st));
             HIP_TRY(nz::launch_clear(d_desc, nullptr, n, ws, d_state, st));
             for (int32_t a = 0; a < n;) {
@@ -661,7 +699,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 const int32_t bx_hook = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(256, (max_site + 1023) / 1024)));
                 const int32_t bx_site = static_cast<int32_t>(std::max<int64_t>(1, std::min<int64_t>(1024, (max_site + 1023) / 1024)));
                 HIP_TRY(nz::launch_prefill(d_desc, d_list, static_cast<int32_t>(prefill_list.size()), bx_hook, bx_site, d_tabs, ws,
-                                           d_state, smax != nullptr, wrap_chunk, per_chunk, st));
+                                           d_state, smax != nullptr, wrap_chunk, per_chunk, st, prefill_events()));
                 // Resolve backoffs inside the chunk: samples whose bulk state already
                 // spans are re-keyed and re-labelled from n0 - b, and if that spans
                 // too from n0 - 3b, so they join this chunk's sweep instead of a
@@ -699,7 +737,7 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                         a = b;
                     }
                     HIP_TRY(nz::launch_prefill(d_desc, d_list, na, bx_hook, bx_site, d_tabs, ws, d_state, smax != nullptr,
-                                               wrap_chunk, per_chunk, st));
+                                               wrap_chunk, per_chunk, st, prefill_events()));
                 }
             }
             if (pe) HIP_TRY(hipEventRecord(pe->ev[2], st));
@@ -780,6 +818,16 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 }
                 g_ms[5] += 1.0;
             }
+            if (pfe) {
+                for (int u = 0; u < pfe->used; ++u) {
+                    for (int k = 0; k < 4; ++k) {
+                        float ms = 0.0f;
+                        HIP_TRY(hipEventElapsedTime(&ms, pfe->ev[u][k], pfe->ev[u][k + 1]));
+                        g_cc_ms[k] += ms;
+                    }
+                    g_cc_ms[4] += 1.0;
+                }
+            }
             if (getenv("NZ_DEBUG_TRACE")) {
                 int cnt[8] = {0};
                 for (int32_t di = 0; di < n; ++di) ++cnt[std::max(0, std::min(7, static_cast<int>(state[di].status)))];
@@ -795,6 +843,8 @@ int run_batch(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, i
                 case NZ_ST_DONE:
                     g_stats[4] += state[di].n0;
                     g_stats[5] += (state[di].nstar > 0 ? state[di].nstar : N) - state[di].n0;
+                    g_job_pre[p.job] += state[di].n0;
+                    g_job_serial[p.job] += (state[di].nstar > 0 ? state[di].nstar : N) - state[di].n0;
                     continue;
                 case NZ_ST_BAND:
                     ++g_stats[1];
@@ -892,6 +942,59 @@ size_t batch_bytes(const nz_job *jobs, int32_t njobs, const Tune &tune)
 
 namespace nz {
 int set_error(int code, const char *msg) { return fail(code, "%s", msg); }
+
+int check_batch_fits(const nz_job *jobs, int32_t njobs, const nz_tuning *tune, size_t ws_bytes)
+{
+    if (njobs < 0 || (njobs > 0 && !jobs)) return fail(NZ_EINVAL, "bad job array");
+    for (int j = 0; j < njobs; ++j)
+        if (int rc = check_job(jobs[j], j)) return rc;
+    Tune t;
+    if (int rc = read_tune(tune, t)) return rc;
+    try {
+        // a chunk's header (sized for as many samples as the batch engine puts
+        // in one chunk) plus the largest single sample of any job, planned as
+        // the engine plans it
+        std::vector<std::pair<uint32_t, int32_t>> tables;
+        size_t tab_entries = 0, largest = 0;
+        int64_t total = 0;
+        int32_t worst = -1;
+        for (int j = 0; j < njobs; ++j) {
+            const nz_job &J = jobs[j];
+            if (J.nsamples <= 0) continue;
+            total += J.nsamples;
+            const auto key = std::make_pair(J.zone_mask, J.L);
+            if (std::find(tables.begin(), tables.end(), key) == tables.end()) {
+                tables.push_back(key);
+                tab_entries += static_cast<size_t>(coordination(J.zone_mask));
+            }
+            Plan p{};
+            p.L = J.L;
+            p.mask = J.zone_mask;
+            p.n0 = J.n0 > 0 ? J.n0 : 0;
+            p.backoff = J.backoff;
+            p.per = J.boundary == NZ_PERIODIC;
+            p.wrap = p.per;
+            const int64_t N = pow5(J.L);
+            p.band_hi = J.band_hi > 0 ? std::min<int64_t>(J.band_hi, N) : default_band_hi(J.L, J.zone_mask, p.n0);
+            if (p.band_hi <= p.n0) p.band_hi = std::min<int64_t>(N, p.n0 + 4096);
+            p.prefix_mul = 1;
+            const size_t b = plan_sizes(p, t.bucket_log2).total;
+            if (b > largest) {
+                largest = b;
+                worst = j;
+            }
+        }
+        if (worst < 0) return NZ_OK;
+        const size_t need = header_bytes(tab_entries, static_cast<int32_t>(std::min<int64_t>(total, kMaxChunk))) + largest;
+        if (need > ws_bytes)
+            return fail(NZ_EWORKSPACE, "job %d (L = %d) needs %zu bytes for one sample; the buffer holds %zu",
+                        worst, jobs[worst].L, need, ws_bytes);
+    } catch (...) {
+        return fail(NZ_ENOMEM, "host allocation failed while sizing the batch");
+    }
+    return NZ_OK;
+}
+
 }  // namespace nz
 
 // ---------------------------------------------------------------------------
@@ -911,6 +1014,25 @@ NZ_API int nz_last_batch_stats(int64_t stats[6])
 {
     if (!stats) return fail(NZ_EINVAL, "stats is NULL");
     for (int k = 0; k < 6; ++k) stats[k] = g_stats[k];
+    return NZ_OK;
+}
+
+NZ_API int nz_last_batch_job_stats(int64_t *serial, int64_t *prefilled, int32_t njobs)
+{
+    if (njobs < 0 || (njobs > 0 && (!serial || !prefilled))) return fail(NZ_EINVAL, "NULL output or njobs < 0");
+    if (static_cast<size_t>(njobs) != g_job_serial.size())
+        return fail(NZ_EINVAL, "the last batch had %zu jobs, not %d", g_job_serial.size(), njobs);
+    for (int32_t j = 0; j < njobs; ++j) {
+        serial[j] = g_job_serial[j];
+        prefilled[j] = g_job_pre[j];
+    }
+    return NZ_OK;
+}
+
+NZ_API int nz_last_batch_cc_timing(double ms[5])
+{
+    if (!ms) return fail(NZ_EINVAL, "ms is NULL");
+    for (int k = 0; k < 5; ++k) ms[k] = g_cc_ms[k];
     return NZ_OK;
 }
 
@@ -1016,6 +1138,8 @@ int run_split(SplitPlan &sp, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_
     std::string err_b;
     int64_t stats_b[6] = {0, 0, 0, 0, 0, 0};
     double ms_b[6] = {0, 0, 0, 0, 0, 0};
+    double cc_b[5] = {0, 0, 0, 0, 0};
+    std::vector<int64_t> serial_b, pre_b;
     const bool timing = g_timing;
     std::thread worker([&]() {
         try {
@@ -1034,6 +1158,9 @@ int run_split(SplitPlan &sp, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_
             stats_b[k] = g_stats[k];
             ms_b[k] = g_ms[k];
         }
+        for (int k = 0; k < 5; ++k) cc_b[k] = g_cc_ms[k];
+        serial_b = g_job_serial;
+        pre_b = g_job_pre;
     });
     int rc_a;
     try {
@@ -1046,6 +1173,21 @@ int run_split(SplitPlan &sp, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_
     for (int k = 0; k < 6; ++k) {
         g_stats[k] += stats_b[k];
         g_ms[k] += ms_b[k];
+    }
+    for (int k = 0; k < 5; ++k) g_cc_ms[k] += cc_b[k];
+    {
+        // per-job figures back in the caller's job order
+        std::vector<int64_t> serial(static_cast<size_t>(njobs), 0), pre(static_cast<size_t>(njobs), 0);
+        for (size_t k = 0; k < sp.job[0].size() && k < g_job_serial.size(); ++k) {
+            serial[sp.index[0][k]] = g_job_serial[k];
+            pre[sp.index[0][k]] = g_job_pre[k];
+        }
+        for (size_t k = 0; k < sp.job[1].size() && k < serial_b.size(); ++k) {
+            serial[sp.index[1][k]] = serial_b[k];
+            pre[sp.index[1][k]] = pre_b[k];
+        }
+        g_job_serial.swap(serial);
+        g_job_pre.swap(pre);
     }
     if (rc_a != NZ_OK) return rc_a;
     if (rc_b != NZ_OK) return fail(rc_b, "%s", err_b.c_str());
@@ -1088,6 +1230,8 @@ NZ_API int nz_sweep_batch(const nz_job *jobs, int32_t njobs, void *d_ws, size_t 
     if (reinterpret_cast<uintptr_t>(d_ws) % kAlign) return fail(NZ_EINVAL, "workspace must be 256-byte aligned");
     Tune t;
     if (int rc = read_tune(tune, t)) return rc;
+    // a workspace that cannot hold one sample is refused before any device call
+    if (int rc = nz::check_batch_fits(jobs, njobs, tune, ws_bytes)) return rc;
     t.dcap = env_dcap();
     hipEvent_t e0 = nullptr, e1 = nullptr;
     if (g_timing) {
@@ -1277,6 +1421,102 @@ NZ_API int nz_convolve_window(const double *Q, int64_t n_lo, int64_t n_hi, int64
         }
         out[k] = swq / sw;
         if (cover) cover[k] = swin / sw;
+    }
+    return NZ_OK;
+}
+
+// ---------------------------------------------------------------------------
+// Learned-prefill planning: the MLP's input rows, its training targets and the
+// turn of its outputs into the jobs' prefill depth, backoff step and key band.
+
+// The size input: L enters through the finite-size-scaling variable
+// L^(-1/nu), nu = 0.5720 (the 5D correlation-length exponent quoted in
+// Sec. II.A.1): the mean of n*/N approaches p_c roughly linearly in it.
+constexpr double kNu5 = 0.5720;
+
+double size_variable(int32_t L) { return std::exp(-std::log(static_cast<double>(L)) / kNu5); }
+
+NZ_API int nz_mlp_size_stats(const int32_t *L, int32_t B, double out[2])
+{
+    if (B < 1 || !L || !out) return fail(NZ_EINVAL, "nz_mlp_size_stats: NULL pointer or B < 1");
+    for (int32_t b = 0; b < B; ++b)
+        if (L[b] < 1 || L[b] > 55) return fail(NZ_EINVAL, "nz_mlp_size_stats: L[%d] = %d outside [1, 55]", b, L[b]);
+    double sum = 0.0;
+    for (int32_t b = 0; b < B; ++b) sum += size_variable(L[b]);
+    const double mean = sum / B;
+    double ss = 0.0;
+    for (int32_t b = 0; b < B; ++b) ss += (size_variable(L[b]) - mean) * (size_variable(L[b]) - mean);
+    const double sd = std::sqrt(ss / B);
+    out[0] = mean;
+    out[1] = sd > 0.0 ? sd : 1.0;
+    return NZ_OK;
+}
+
+NZ_API int nz_mlp_features(const uint32_t *zone_mask, const int32_t *L, int32_t B, double size_mean, double size_std,
+                           float *x)
+{
+    if (B < 1 || !zone_mask || !L || !x) return fail(NZ_EINVAL, "nz_mlp_features: NULL pointer or B < 1");
+    if (!(size_std > 0.0)) return fail(NZ_EINVAL, "nz_mlp_features: size_std must be positive");
+    for (int32_t b = 0; b < B; ++b) {
+        if (zone_mask[b] < 1 || zone_mask[b] > 127 || L[b] < 1 || L[b] > 55)
+            return fail(NZ_EINVAL, "nz_mlp_features: row %d has zone_mask %u, L %d", b, zone_mask[b], L[b]);
+        for (int k = 0; k < 7; ++k) x[8 * b + k] = static_cast<float>((zone_mask[b] >> k) & 1u);
+        x[8 * b + 7] = static_cast<float>((size_variable(L[b]) - size_mean) / size_std);
+    }
+    return NZ_OK;
+}
+
+NZ_API int nz_prefill_target(const int32_t *nstar, int64_t nsamples, int32_t L, double out[5])
+{
+    if (nsamples < 0 || (nsamples > 0 && !nstar) || !out || L < 1 || L > 55)
+        return fail(NZ_EINVAL, "nz_prefill_target: bad arguments");
+    const double N = static_cast<double>(pow5(L));
+    long double s1 = 0.0L;
+    int64_t count = 0;
+    for (int64_t k = 0; k < nsamples; ++k)
+        if (nstar[k] > 0) {
+            s1 += static_cast<long double>(nstar[k]) / N;
+            ++count;
+        }
+    if (count == 0) return fail(NZ_EINVAL, "nz_prefill_target: no sample spans");
+    const long double mean = s1 / count;
+    long double ss = 0.0L;
+    for (int64_t k = 0; k < nsamples; ++k)
+        if (nstar[k] > 0) {
+            const long double d = static_cast<long double>(nstar[k]) / N - mean;
+            ss += d * d;
+        }
+    const double sd = std::max(static_cast<double>(std::sqrt(ss / count)), 0.5 / N);
+    out[0] = static_cast<double>(count);
+    out[1] = static_cast<double>(mean);
+    out[2] = sd;
+    out[3] = std::log(out[1]);
+    out[4] = std::log(sd);
+    return NZ_OK;
+}
+
+NZ_API int nz_prefill_plan(const float *y, nz_job *jobs, int32_t njobs, double k_sigma, double band_sigma,
+                           int32_t plain)
+{
+    if (njobs < 0 || (njobs > 0 && (!y || !jobs))) return fail(NZ_EINVAL, "nz_prefill_plan: NULL pointer or njobs < 0");
+    if (!(k_sigma >= 0.0) || !(band_sigma >= 0.0)) return fail(NZ_EINVAL, "nz_prefill_plan: negative sigma factor");
+    for (int32_t j = 0; j < njobs; ++j)
+        if (jobs[j].L < 1 || jobs[j].L > 55) return fail(NZ_EINVAL, "nz_prefill_plan: job %d has L = %d", j, jobs[j].L);
+    for (int32_t j = 0; j < njobs; ++j) {
+        nz_job &J = jobs[j];
+        const int64_t N = pow5(J.L);
+        const double mean = std::exp(static_cast<double>(y[2 * j]));
+        const double sd = std::exp(static_cast<double>(y[2 * j + 1]));
+        const double hi = std::ceil((mean + band_sigma * sd) * static_cast<double>(N)) + 1024.0;
+        J.band_hi = hi >= static_cast<double>(N) ? N : static_cast<int64_t>(hi);
+        if (plain) {
+            J.n0 = -1;
+            continue;
+        }
+        const double d0 = std::floor((mean - k_sigma * sd) * static_cast<double>(N));
+        J.n0 = d0 <= 0.0 ? 0 : (d0 >= static_cast<double>(N - 1) ? N - 1 : static_cast<int64_t>(d0));
+        const double b = std::ceil(k_sigma * sd * static_cast<double>(N));
+        J.backoff = b >= static_cast<double>(N) ? N : static_cast<int64_t>(b);
     }
     return NZ_OK;
 }

@@ -2066,9 +2066,13 @@ hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int3
 
 hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nlist, int32_t bx_hook, int32_t bx_site,
                           const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, bool wrap, bool periodic,
-                          hipStream_t st)
+                          hipStream_t st, hipEvent_t *ev)
 {
     if (nlist <= 0) return hipSuccess;
+    auto mark = [&](int k) {
+        if (ev) (void)hipEventRecord(ev[k], st);
+    };
+    mark(0);
     const uint32_t slots8 = static_cast<uint32_t>((nlist + 7) / 8) * 8u;
     if (wrap) {
         hipLaunchKernelGGL(nz_hookw_kernel, dim3(static_cast<uint32_t>(bx_hook) * slots8), dim3(256), 0, st, desc, list,
@@ -2077,6 +2081,10 @@ hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nli
                            nlist, bx_site, ws, state);
         hipLaunchKernelGGL(nz_accumw_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
                            nlist, bx_site, ws, state);
+        mark(1);
+        mark(2);
+        mark(3);
+        mark(4);
         return hipGetLastError();
     }
     if (periodic)
@@ -2085,12 +2093,16 @@ hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nli
     else
         hipLaunchKernelGGL(nz_hook_kernel<false>, dim3(static_cast<uint32_t>(bx_hook) * slots8), dim3(256), 0, st, desc,
                            list, nlist, bx_hook, tabs, ws, state);
+    mark(1);
     hipLaunchKernelGGL(nz_compress_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
                        nlist, bx_site, ws, state);
+    mark(2);
     hipLaunchKernelGGL(nz_accum_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list, nlist,
                        bx_site, ws, state);
+    mark(3);
     hipLaunchKernelGGL(nz_expand_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
                        nlist, bx_site, ws, state);
+    mark(4);
     if (smax)
         hipLaunchKernelGGL(nz_rootmax_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
                            nlist, bx_site, ws, state);

@@ -2,6 +2,7 @@
 #pragma once
 #include <hip/hip_runtime.h>
 
+#include "../../include/nz.h"
 #include "nz_internal.h"
 
 namespace nz {
@@ -27,9 +28,11 @@ hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int3
 // smax: also the largest cluster of each smax-mode sample's prefilled state.
 // wrap: the listed samples are periodic first-wrap samples (64-bit entries).
 // periodic: the listed samples have periodic coordinates (all or none of them).
+// ev (may be NULL): five events recorded before the hook, after it, after
+// compress, after the size pass and after expand (free-boundary samples).
 hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nlist, int32_t bx_hook, int32_t bx_site,
                           const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, bool wrap, bool periodic,
-                          hipStream_t st);
+                          hipStream_t st, hipEvent_t *ev = nullptr);
 
 // out[0..w) += sum over the chunk's finished samples 0..nsamp-1 of their S_max windows.
 hipError_t launch_winsum(const NzSample *desc, const NzState *state, int32_t nsamp, int32_t w, const uint8_t *ws,
@@ -50,5 +53,10 @@ uint32_t block_lds_words();
 // site per step, state in HBM, 256-thread workgroups.
 hipError_t launch_wrap_sweep(int nch, const NzSweepArgs &a, int32_t *nstar, int32_t *mass, const int32_t *out_index,
                              int grid, hipStream_t st);
+
+// Host side (nz_api.cpp): whether a chunk header and the largest single
+// sample of the jobs fit a workspace of ws_bytes (NZ_EWORKSPACE otherwise).
+int set_error(int code, const char *msg);
+int check_batch_fits(const nz_job *jobs, int32_t njobs, const nz_tuning *tune, size_t ws_bytes);
 
 }  // namespace nz

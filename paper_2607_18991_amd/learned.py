@@ -47,16 +47,9 @@ def init_params(seed: int = 0) -> np.ndarray:
     return flat
 
 
-# The size input: ln L enters through the finite-size-scaling variable
-# exp(-ln L / nu) = L^(-1/nu), nu_5 = 0.5720 (the 5D correlation-length exponent
-# quoted in Sec. II.A.3).  The mean of n*/N approaches p_c roughly linearly in it,
-# so lattices larger than the training ones sit just beyond the training range
-# where the curves flatten, instead of far out on a ln L axis.
+# The size input is the finite-size-scaling variable L^(-1/nu), standardised
+# over the training set; the library forms it (nz_mlp_features).
 NU5 = 0.5720
-
-
-def size_variable(L: int) -> float:
-    return math.exp(-math.log(L) / NU5)
 
 
 class PrefillModel:
@@ -90,12 +83,11 @@ class PrefillModel:
 
     # ---------------------------------------------------------------- inference
     def features(self, masks, Ls) -> np.ndarray:
-        rows = [zone_bits(int(m)) + [(size_variable(int(L)) - self.size_mean) / self.size_std]
-                for m, L in zip(masks, Ls)]
-        return np.array(rows, dtype=np.float32).reshape(-1, IN)
+        return nz.nz_mlp_features(masks, Ls, self.size_mean, self.size_std)
 
-    def predict(self, masks, Ls, stream=None):
-        """Predicted (mean, std) of n*/N per (mask, L), via the forward kernel."""
+    def forward(self, masks, Ls, stream=None) -> np.ndarray:
+        """The MLP's outputs (ln mean, ln std of n*/N) per (mask, L), via the
+        forward kernel."""
         import torch
 
         x = torch.from_numpy(self.features(masks, Ls)).cuda()
@@ -108,59 +100,46 @@ class PrefillModel:
         y = torch.empty((B, OUT), dtype=torch.float32, device="cuda")
         act = torch.empty((B, nz.NZ_MLP_NACT), dtype=torch.float32, device="cuda")
         nz.nz_mlp_forward(pb, x, y, act, stream=stream)
-        out = y.cpu().numpy().astype(np.float64)
+        return y.cpu().numpy()
+
+    def predict(self, masks, Ls, stream=None):
+        """Predicted (mean, std) of n*/N per (mask, L)."""
+        out = self.forward(masks, Ls, stream).astype(np.float64)
         return np.exp(out[:, 0]), np.exp(out[:, 1])
 
     def plan(self, jobs, k_sigma: float = 3.0, band_sigma: float = 5.0):
-        """Copies of the job dicts with the learned n0, backoff step and band."""
-        jobs = [dict(j) for j in jobs]
-        mean, std = self.predict([j["zone_mask"] for j in jobs], [j["L"] for j in jobs])
-        for j, mu, sd in zip(jobs, mean, std):
-            N = int(j["L"]) ** 5
-            n0 = int(math.floor((mu - k_sigma * sd) * N))
-            j["n0"] = max(0, min(N - 1, n0))
-            j["backoff"] = int(math.ceil(k_sigma * sd * N))
-            j["band_hi"] = min(N, int(math.ceil((mu + band_sigma * sd) * N)) + 1024)
-        return jobs
+        """Copies of the job dicts with the learned n0, backoff step and band
+        (nz_prefill_plan)."""
+        y = self.forward([j["zone_mask"] for j in jobs], [j["L"] for j in jobs])
+        return nz.nz_prefill_plan(y, jobs, k_sigma, band_sigma)
 
 
 def plan_band_only(model: PrefillModel, jobs, band_sigma: float = 5.0):
     """Plain sweeps (no prefill) with the learned band size, so that plain and
     learned runs differ only in the prefill."""
-    mean, std = model.predict([j["zone_mask"] for j in jobs], [j["L"] for j in jobs])
-    out = []
-    for j, mu, sd in zip(jobs, mean, std):
-        j = dict(j)
-        N = int(j["L"]) ** 5
-        j["n0"] = -1
-        j["band_hi"] = min(N, int(math.ceil((mu + band_sigma * sd) * N)) + 1024)
-        out.append(j)
-    return out
+    y = model.forward([j["zone_mask"] for j in jobs], [j["L"] for j in jobs])
+    return nz.nz_prefill_plan(y, jobs, 0.0, band_sigma, plain=True)
 
 
 def aggregate(L: int, mask: int, nstar: np.ndarray) -> dict:
-    """Training target of one lattice: ln mean and ln std of n*/N over samples
-    that span."""
-    N = L**5
-    f = nstar[nstar > 0].astype(np.float64) / N
-    sd = max(float(f.std()), 0.5 / N)
-    return {"L": L, "mask": mask, "count": int(len(f)), "mean": float(f.mean()), "std": sd}
+    """Training target of one lattice: mean and std of n*/N over the samples
+    that span (nz_prefill_target)."""
+    count, mean, sd, ln_mean, ln_sd = nz.nz_prefill_target(nstar, L)
+    return {"L": L, "mask": mask, "count": count, "mean": mean, "std": sd, "ln_mean": ln_mean, "ln_std": ln_sd}
 
 
 def train(points, steps: int = 3000, lr: float = 3e-3, seed: int = 0, log_every: int = 0,
           wd: float = 0.0) -> PrefillModel:
-    """Fit the MLP to aggregates [{'L','mask','count','mean','std'}] with the
+    """Fit the MLP to aggregates [{'L','mask','count','ln_mean','ln_std'}] with the
     device kernels: forward, weighted squared error, backward, Adam."""
     import torch
 
-    Ls = np.array([p["L"] for p in points], dtype=np.float64)
-    sv = np.array([size_variable(int(L)) for L in Ls])
+    Ls = np.array([p["L"] for p in points], dtype=np.int32)
     w = np.array([p["count"] for p in points], dtype=np.float64)
-    s_mean = float(sv.mean())
-    s_std = float(sv.std()) if sv.std() > 0 else 1.0
+    s_mean, s_std = nz.nz_mlp_size_stats(Ls)
     model = PrefillModel(init_params(seed), s_mean, s_std)
     x = torch.from_numpy(model.features([p["mask"] for p in points], [p["L"] for p in points])).cuda()
-    tgt = torch.from_numpy(np.array([[math.log(p["mean"]), math.log(p["std"])] for p in points],
+    tgt = torch.from_numpy(np.array([[p["ln_mean"], p["ln_std"]] for p in points],
                                     dtype=np.float32)).cuda()
     # every lattice counts, with a mild preference for the better-sampled ones
     wt = torch.from_numpy(np.sqrt(w).astype(np.float32)).cuda()

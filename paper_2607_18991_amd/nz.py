@@ -30,7 +30,8 @@ EXPORTS = (
     "nz_last_error", "nz_abi_version", "nz_coordination", "nz_sweep", "nz_canonical",
     "nz_batch_workspace_bytes", "nz_sweep_batch", "nz_last_batch_stats",
     "nz_mlp_forward", "nz_mlp_backward", "nz_mlp_adam", "nz_set_timing", "nz_last_batch_timing",
-    "nz_mlp_loss", "nz_smax_window", "nz_convolve_window",
+    "nz_mlp_loss", "nz_smax_window", "nz_convolve_window", "nz_last_batch_job_stats", "nz_last_batch_cc_timing",
+    "nz_mlp_size_stats", "nz_mlp_features", "nz_prefill_target", "nz_prefill_plan",
 )
 
 
@@ -90,6 +91,18 @@ def lib():
     L.nz_sweep_batch.restype = ctypes.c_int
     L.nz_last_batch_stats.argtypes = [P]
     L.nz_last_batch_stats.restype = ctypes.c_int
+    L.nz_last_batch_job_stats.argtypes = [P, P, i32]
+    L.nz_last_batch_job_stats.restype = ctypes.c_int
+    L.nz_last_batch_cc_timing.argtypes = [P]
+    L.nz_last_batch_cc_timing.restype = ctypes.c_int
+    L.nz_mlp_size_stats.argtypes = [P, i32, P]
+    L.nz_mlp_size_stats.restype = ctypes.c_int
+    L.nz_mlp_features.argtypes = [P, P, i32, ctypes.c_double, ctypes.c_double, P]
+    L.nz_mlp_features.restype = ctypes.c_int
+    L.nz_prefill_target.argtypes = [P, i64, i32, P]
+    L.nz_prefill_target.restype = ctypes.c_int
+    L.nz_prefill_plan.argtypes = [P, P, i32, ctypes.c_double, ctypes.c_double, i32]
+    L.nz_prefill_plan.restype = ctypes.c_int
     L.nz_set_timing.argtypes = [ctypes.c_int]
     L.nz_set_timing.restype = ctypes.c_int
     L.nz_last_batch_timing.argtypes = [P]
@@ -230,6 +243,20 @@ def nz_last_batch_stats() -> dict:
             "prefilled_sites": int(s[4]), "serial_steps": int(s[5])}
 
 
+def nz_last_batch_job_stats(njobs: int):
+    """(serial, prefilled) int64 arrays per job of the last batch."""
+    a = np.zeros(max(njobs, 1), dtype=np.int64)
+    b = np.zeros(max(njobs, 1), dtype=np.int64)
+    _check(lib().nz_last_batch_job_stats(_np_ptr(a), _np_ptr(b), njobs))
+    return a[:njobs], b[:njobs]
+
+
+def nz_last_batch_cc_timing() -> dict:
+    ms = np.zeros(5, dtype=np.float64)
+    _check(lib().nz_last_batch_cc_timing(_np_ptr(ms)))
+    return {"hook_ms": ms[0], "compress_ms": ms[1], "accum_ms": ms[2], "expand_ms": ms[3], "dispatches": int(ms[4])}
+
+
 def nz_set_timing(enable: bool) -> None:
     _check(lib().nz_set_timing(int(bool(enable))))
 
@@ -239,6 +266,47 @@ def nz_last_batch_timing() -> dict:
     _check(lib().nz_last_batch_timing(_np_ptr(ms)))
     return {"keys_ms": ms[0], "cc_ms": ms[1], "sort_ms": ms[2], "sweep_ms": ms[3], "total_ms": ms[4],
             "sweep_launches": int(ms[5])}
+
+
+# ---------------------------------------------------------------- learned-prefill planning (host)
+def nz_mlp_size_stats(Ls):
+    L = np.ascontiguousarray(Ls, dtype=np.int32)
+    out = np.zeros(2, dtype=np.float64)
+    _check(lib().nz_mlp_size_stats(_np_ptr(L), len(L), _np_ptr(out)))
+    return float(out[0]), float(out[1])
+
+
+def nz_mlp_features(masks, Ls, size_mean: float, size_std: float) -> np.ndarray:
+    m = np.ascontiguousarray(masks, dtype=np.uint32)
+    L = np.ascontiguousarray(Ls, dtype=np.int32)
+    x = np.zeros((max(len(m), 1), 8), dtype=np.float32)
+    _check(lib().nz_mlp_features(_np_ptr(m), _np_ptr(L), len(m), size_mean, size_std, _np_ptr(x)))
+    return x[: len(m)]
+
+
+def nz_prefill_target(nstar, L: int):
+    """(samples used, mean, std, ln mean, ln std) of n*/N over the samples
+    that span."""
+    ns = np.ascontiguousarray(nstar, dtype=np.int32)
+    out = np.zeros(5, dtype=np.float64)
+    _check(lib().nz_prefill_target(_np_ptr(ns), len(ns), L, _np_ptr(out)))
+    return int(out[0]), float(out[1]), float(out[2]), float(out[3]), float(out[4])
+
+
+def nz_prefill_plan(y, jobs, k_sigma: float, band_sigma: float, plain: bool = False):
+    """Copies of the job dicts with n0, backoff and band_hi from the MLP
+    outputs y[j] = (ln mean, ln std)."""
+    yy = np.ascontiguousarray(y, dtype=np.float32).reshape(-1, 2)
+    jobs = [dict(j) for j in jobs]
+    arr, n = make_jobs(jobs)
+    _check(lib().nz_prefill_plan(_np_ptr(yy), ctypes.cast(arr, ctypes.c_void_p), n, k_sigma, band_sigma,
+                                 int(bool(plain))))
+    for k, j in enumerate(jobs):
+        j["band_hi"] = int(arr[k].band_hi)
+        j["n0"] = int(arr[k].n0)
+        if not plain:
+            j["backoff"] = int(arr[k].backoff)
+    return jobs
 
 
 # ---------------------------------------------------------------- MLP kernels

@@ -3,9 +3,10 @@
 From a kernel-trace run (--kernel-trace --stats) and two counter runs
 (--pmc FETCH_SIZE, --pmc WRITE_SIZE) of the same command, it writes
 profiles/<name>.md (per-kernel time and HBM traffic, with the commands) and
-profiles/<name>.json, the traffic per launch of the sweep kernel together
-with the SHA-1 of the kernel and launch-planner sources it was measured on;
-bench.py reports that traffic only while those sources are unchanged.
+profiles/<name>.json, the traffic of every kernel over the counter runs'
+steps together with the SHA-1 of the kernel and launch-planner sources it was
+measured on; bench.py reports that traffic only while those sources are
+unchanged.
 
 Counter scaling: FETCH_SIZE and WRITE_SIZE are KiB per dispatch; a plain
 device copy of 1 GiB reads FETCH_SIZE = 0.5 GiB and WRITE_SIZE = 1 GiB on
@@ -70,6 +71,36 @@ def counters(dirname: str, counter: str):
     return agg
 
 
+def timeline(dirname: str, marker: str = "nzmlp::mlp_forward_kernel"):
+    """The last bench step of a kernel-trace run as one row per dispatch:
+    (queue, kernel, start ms, end ms) relative to the step's first dispatch.
+    Steps start with the prefill MLP's forward kernel (every step plans its
+    jobs), so the last step is everything from the last such dispatch on."""
+    rows = []
+    for r in csv.DictReader(open(_find(dirname, "kernel_trace.csv"))):
+        q = r.get("Stream_Id") or r.get("Queue_Id") or "0"
+        rows.append((int(r["Start_Timestamp"]), int(r["End_Timestamp"]), q, short(r["Kernel_Name"])))
+    rows.sort()
+    starts = [i for i, row in enumerate(rows) if row[3].startswith(marker)]
+    first = starts[-1] if starts else 0
+    t0 = rows[first][0]
+    return [(q, k, (a - t0) / 1e6, (b - t0) / 1e6) for a, b, q, k in rows[first:]]
+
+
+def timeline_md(rows, title: str):
+    """Markdown of timeline(): per queue, its kernels in start order, plus the
+    busy span of each queue."""
+    lines = [f"### {title}", "", "| queue | kernel | start ms | end ms | ms |", "|---|---|---|---|---|"]
+    for q in sorted(set(r[0] for r in rows), key=str):
+        mine = [r for r in rows if r[0] == q]
+        for _, k, a, b in mine:
+            if b - a >= 0.05:
+                lines.append(f"| {q} | `{k}` | {a:.2f} | {b:.2f} | {b - a:.2f} |")
+        lines.append(f"| {q} | **span** | {min(r[2] for r in mine):.2f} | {max(r[3] for r in mine):.2f} | "
+                     f"{max(r[3] for r in mine) - min(r[2] for r in mine):.2f} |")
+    return lines
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--stats", required=True, help="output folder of the --kernel-trace --stats run")
@@ -81,8 +112,10 @@ def main():
     ap.add_argument("--l2", default=None, help="output folder of a --pmc TCC_HIT_sum TCC_MISS_sum run (optional)")
     ap.add_argument("--steps", type=int, default=2, help="bench steps in the stats run (warm-up included)")
     ap.add_argument("--sweep", default="nz::nz_sweep_kernel")
-    ap.add_argument("--keys", default="nz::nz_keys_kernel")
+    ap.add_argument("--counter-steps", type=int, default=1, help="bench steps in each counter run")
     ap.add_argument("--outdir", default=os.path.join(HERE, "..", "profiles"))
+    ap.add_argument("--timeline", action="store_true",
+                    help="add the last step's dispatches per queue from the --stats run's kernel trace")
     args = ap.parse_args()
 
     stats = kernel_stats(args.stats)
@@ -115,18 +148,23 @@ def main():
                 continue
             n = max(hit.get(k, [0, 0])[0], miss.get(k, [0, 0])[0])
             lines.append(f"| `{k}` | {n} | {(h + mi) / 1e6:.1f} | {h / (h + mi):.3f} |")
-    sweep_f = sum(v[1] for k, v in fetch.items() if k.startswith(args.sweep)) * 1024 * FETCH_SCALE
-    sweep_w = sum(v[1] for k, v in write.items() if k.startswith(args.sweep)) * 1024 * WRITE_SCALE
-    launches = max(1, sum(v[0] for k, v in fetch.items() if k.startswith(args.sweep)))
-    rec = {"kernel": args.sweep, "launches": launches, "fetch_bytes_per_launch": sweep_f / launches,
-           "write_bytes_per_launch": sweep_w / launches, "source_sha1": source_sha1()}
-    # the keys kernel (the counter runs time one step): bytes over the step's launches
-    keys_f = sum(v[1] for k, v in fetch.items() if k.startswith(args.keys)) * 1024 * FETCH_SCALE
-    keys_w = sum(v[1] for k, v in write.items() if k.startswith(args.keys)) * 1024 * WRITE_SCALE
-    rec["keys"] = {"kernel": args.keys, "fetch_bytes_per_step": keys_f, "write_bytes_per_step": keys_w,
-                   "dispatches": sum(v[0] for k, v in fetch.items() if k.startswith(args.keys))}
-    lines += ["", f"Sweep kernel per launch: {rec['fetch_bytes_per_launch'] / 1e9:.3f} GB fetched, "
-                  f"{rec['write_bytes_per_launch'] / 1e9:.3f} GB written over {launches} launches; kernel source "
+    if args.timeline:
+        lines += [""] + timeline_md(timeline(args.stats), "Timeline of the last step (dispatches of 0.05 ms or more)")
+    # per kernel (template instances summed): dispatches and bytes over the
+    # counter runs, which time args.counter_steps bench steps
+    kern = defaultdict(lambda: {"dispatches": 0, "fetch_bytes": 0.0, "write_bytes": 0.0})
+    for k, (n, v) in fetch.items():
+        base = k.split("<")[0]
+        kern[base]["dispatches"] += n
+        kern[base]["fetch_bytes"] += v * 1024 * FETCH_SCALE
+    for k, (n, v) in write.items():
+        base = k.split("<")[0]
+        kern[base]["write_bytes"] += v * 1024 * WRITE_SCALE
+    rec = {"steps": args.counter_steps, "kernels": dict(kern), "source_sha1": source_sha1()}
+    sw = kern.get(args.sweep, {"dispatches": 0, "fetch_bytes": 0.0, "write_bytes": 0.0})
+    launches = max(1, sw["dispatches"])
+    lines += ["", f"Sweep kernel per launch: {sw['fetch_bytes'] / launches / 1e9:.3f} GB fetched, "
+                  f"{sw['write_bytes'] / launches / 1e9:.3f} GB written over {launches} launches; kernel source "
                   f"SHA-1 {rec['source_sha1'][:12]}.", ""]
     os.makedirs(args.outdir, exist_ok=True)
     with open(os.path.join(args.outdir, args.name + ".md"), "w") as f:

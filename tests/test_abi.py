@@ -168,3 +168,60 @@ def test_split_needs_256_samples_in_each_group(monkeypatch):
     assert s == o
     s, o = sizes(4000, 255)
     assert s == o
+
+
+def test_batch_rejects_a_workspace_below_one_sample():
+    """nz_sweep_batch refuses a workspace that cannot hold one sample with
+    NZ_EWORKSPACE and a message, before any launch."""
+    import ctypes
+
+    arr, n = nz.make_jobs([dict(L=16, zone_mask=1, seed=1, nsamples=4)])
+    # a 256-byte-aligned host address stands in for the device buffer: the size
+    # check comes first, so nothing is ever written there
+    buf = np.zeros(4096 // 8 + 64, dtype=np.uint64)
+    addr = (buf.ctypes.data + 255) // 256 * 256
+    dn = np.zeros(4, dtype=np.int32)
+    rc = nz.lib().nz_sweep_batch(ctypes.cast(arr, ctypes.c_void_p), n, ctypes.c_void_p(addr), 1024,
+                                 dn.ctypes.data_as(ctypes.c_void_p), None, None, None, None)
+    assert rc == nz.NZ_EWORKSPACE
+    assert b"needs" in nz.lib().nz_last_error()
+
+
+def test_prefill_planning_host_calls():
+    """The learned prefill's host arithmetic behind the ABI: the MLP's input
+    rows, the size statistics, the training target of a lattice and the plan
+    (n0, backoff, band) from the MLP's outputs, including the clamps."""
+    Ls = np.array([4, 8, 16, 24], dtype=np.int32)
+    sv = Ls.astype(np.float64) ** (-1.0 / 0.5720)
+    mean, std = nz.nz_mlp_size_stats(Ls)
+    assert np.isclose(mean, sv.mean(), rtol=1e-12) and np.isclose(std, sv.std(), rtol=1e-12)
+    m8, s8 = nz.nz_mlp_size_stats([8, 8])
+    assert np.isclose(m8, 8.0 ** (-1 / 0.5720), rtol=1e-14) and s8 == 1.0
+    x = nz.nz_mlp_features([0x01, 0x55, 0x7F, 0x40], Ls, mean, std)
+    assert x.shape == (4, 8) and x.dtype == np.float32
+    assert (x[:, :7] == np.array([[(m >> k) & 1 for k in range(7)] for m in (0x01, 0x55, 0x7F, 0x40)])).all()
+    assert np.allclose(x[:, 7], ((sv - mean) / std).astype(np.float32), rtol=1e-6)
+    # training target: spanning samples only, population std floored at 0.5/N
+    ns = np.array([100, 0, 120, 140, 0], dtype=np.int32)
+    cnt, m, s, lm, ls = nz.nz_prefill_target(ns, 4)
+    f = np.array([100, 120, 140]) / 1024.0
+    assert cnt == 3 and np.isclose(m, f.mean(), rtol=1e-14) and np.isclose(s, f.std(), rtol=1e-12)
+    assert np.isclose(lm, np.log(m)) and np.isclose(ls, np.log(s))
+    assert nz.nz_prefill_target(np.array([7, 7], dtype=np.int32), 4)[2] == 0.5 / 1024
+    with pytest.raises(nz.NzError):
+        nz.nz_prefill_target(np.array([0, 0], dtype=np.int32), 4)
+    # plan: n0 = floor((mu - 3 sd) N) clamped, backoff = ceil(3 sd N), band = ceil((mu + 5 sd) N) + 1024
+    jobs = [dict(L=16, zone_mask=1, seed=1, nsamples=4), dict(L=4, zone_mask=1, seed=1, nsamples=4),
+            dict(L=8, zone_mask=3, seed=2, nsamples=1)]
+    y = np.log(np.array([[0.14, 0.004], [0.02, 0.05], [0.9, 0.2]], dtype=np.float64)).astype(np.float32)
+    out = nz.nz_prefill_plan(y, jobs, 3.0, 5.0)
+    mu, sd = np.exp(y[:, 0].astype(np.float64)), np.exp(y[:, 1].astype(np.float64))
+    N = np.array([16**5, 4**5, 8**5])
+    assert out[0]["n0"] == int(np.floor((mu[0] - 3 * sd[0]) * N[0]))
+    assert out[1]["n0"] == 0                                   # mean - 3 std < 0
+    assert out[2]["band_hi"] == N[2]                           # band beyond the lattice
+    assert out[0]["backoff"] == int(np.ceil(3 * sd[0] * N[0]))
+    assert out[0]["band_hi"] == int(np.ceil((mu[0] + 5 * sd[0]) * N[0])) + 1024
+    assert jobs[0].get("n0") is None                           # the caller's dicts are not touched
+    plain = nz.nz_prefill_plan(y, jobs, 0.0, 5.0, plain=True)
+    assert all(j["n0"] == -1 for j in plain) and plain[0]["band_hi"] == out[0]["band_hi"]

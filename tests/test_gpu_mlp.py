@@ -82,7 +82,8 @@ def test_training_reduces_loss_on_smooth_targets():
         for m in range(1, 128, 3):
             z = nz.nz_coordination(m)
             mean = 1.55 / (z + 1.0) * (1 + 1.0 / L)
-            pts.append(dict(L=L, mask=m, count=100, mean=mean, std=mean * 0.5 * L**-1.5))
+            std = mean * 0.5 * L**-1.5
+            pts.append(dict(L=L, mask=m, count=100, mean=mean, std=std, ln_mean=np.log(mean), ln_std=np.log(std)))
     model = learned.train(pts, steps=600, lr=3e-3, log_every=100)
     hist = model.meta["loss_history"]
     assert hist[-1][1] < 0.05 * hist[0][1]
