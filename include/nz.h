@@ -216,6 +216,36 @@ int nz_sweep_batch(const nz_job *jobs, int32_t njobs, void *d_ws, size_t ws_byte
                    int32_t *d_nstar, int32_t *d_mass, int32_t *h_backoffs,
                    const nz_tuning *tune, void *stream);
 
+/*
+ * nz_sweep_batch_static -- nz_sweep_batch for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops, hosts
+ * that forbid allocation calls).  The caller passes jobs and outputs only; the
+ * workspace is a device buffer of NZ_STATIC_SCRATCH_BYTES that the library
+ * holds on every device it has run on until the process ends.  No device or
+ * host memory is allocated by the call: no hipMalloc or hipFree, no stream,
+ * event or thread is created (the batch runs as one group on `stream`, and
+ * nz_set_timing has no effect on it).
+ *   jobs, njobs, d_nstar, d_mass, h_backoffs, tune, stream: as for
+ *                  nz_sweep_batch (d_nstar, d_mass DEVICE, written in job
+ *                  order; results are in place when the call returns);
+ * Errors: NZ_EWORKSPACE, before any device call, when one sample of some job
+ * (with the chunk header) does not fit the buffer: at the default key band
+ * every L <= 24 fits; a sample whose band must be redone wider than the
+ * buffer holds fails with NZ_EWORKSPACE during the call.  Samples are run in
+ * as many chunks as the buffer needs, so large batches are slower than with a
+ * full-size workspace, never different.
+ * The buffer keeps the last call's contents; every call clears what it needs.
+ * Calls on one device are serialised by a lock inside the library, so calls
+ * from several host threads of one process queue up; each process has its own
+ * copy of the buffer.
+ */
+#define NZ_STATIC_SCRATCH_BYTES ((size_t)256 << 20)
+int nz_sweep_batch_static(const nz_job *jobs, int32_t njobs, int32_t *d_nstar, int32_t *d_mass,
+                          int32_t *h_backoffs, const nz_tuning *tune, void *stream);
+
+/* Size of that buffer in bytes (NZ_STATIC_SCRATCH_BYTES). */
+size_t nz_static_scratch_bytes(void);
+
 /* Statistics of the last nz_sweep_batch on the calling thread, stats[0..5]:
  * chunks, samples redone because their band ran out, because a bucket
  * overflowed, backoffs, sites occupied by the bulk prefill (summed over the

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libnz.so")
 PEAK_LIB = os.path.join(HERE, "libnzpeak.so")
-SOURCES = ["nz_kernels.hip", "nz_mlp.hip", "nz_api.cpp"]
+SOURCES = ["nz_kernels.hip", "nz_mlp.hip", "nz_static.hip", "nz_api.cpp"]
 
 HIPCC_FLAGS = [
     "--offload-arch=gfx950",

@@ -995,6 +995,33 @@ int check_batch_fits(const nz_job *jobs, int32_t njobs, const nz_tuning *tune, s
     return NZ_OK;
 }
 
+int run_batch_one_group(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_t *d_nstar,
+                        int32_t *d_mass, int32_t *h_backoffs, const nz_tuning *tune, hipStream_t st)
+{
+    int64_t total = 0;
+    for (int j = 0; j < njobs; ++j) total += jobs[j].nsamples;
+    if (total == 0) {
+        for (int k = 0; k < 6; ++k) g_stats[k] = 0;
+        if (h_backoffs)
+            for (int j = 0; j < njobs; ++j) h_backoffs[j] = 0;
+        return NZ_OK;
+    }
+    if (!d_nstar) return fail(NZ_EINVAL, "n* output is NULL");
+    Tune t;
+    if (int rc = read_tune(tune, t)) return rc;
+    t.dcap = env_dcap();
+    // no phase events: this path creates no runtime objects
+    const bool timing = g_timing;
+    g_timing = false;
+    int rc;
+    try {
+        rc = run_batch(jobs, njobs, ws, ws_bytes, d_nstar, d_mass, h_backoffs, t, st);
+    } catch (...) {
+        rc = fail(NZ_ENOMEM, "host allocation failed");
+    }
+    g_timing = timing;
+    return rc;
+}
 }  // namespace nz
 
 // ---------------------------------------------------------------------------

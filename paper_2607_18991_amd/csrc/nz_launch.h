@@ -54,9 +54,13 @@ uint32_t block_lds_words();
 hipError_t launch_wrap_sweep(int nch, const NzSweepArgs &a, int32_t *nstar, int32_t *mass, const int32_t *out_index,
                              int grid, hipStream_t st);
 
-// Host side (nz_api.cpp): whether a chunk header and the largest single
-// sample of the jobs fit a workspace of ws_bytes (NZ_EWORKSPACE otherwise).
+// Host side of nz_sweep_batch_static (nz_api.cpp): whether a chunk header and
+// the largest single sample of the jobs fit a buffer of ws_bytes; and
+// the batch engine run as one group on one stream with no events, threads or
+// streams of its own.
 int set_error(int code, const char *msg);
 int check_batch_fits(const nz_job *jobs, int32_t njobs, const nz_tuning *tune, size_t ws_bytes);
+int run_batch_one_group(const nz_job *jobs, int32_t njobs, uint8_t *ws, size_t ws_bytes, int32_t *d_nstar,
+                        int32_t *d_mass, int32_t *h_backoffs, const nz_tuning *tune, hipStream_t st);
 
 }  // namespace nz

@@ -30,7 +30,8 @@ EXPORTS = (
     "nz_last_error", "nz_abi_version", "nz_coordination", "nz_sweep", "nz_canonical",
     "nz_batch_workspace_bytes", "nz_sweep_batch", "nz_last_batch_stats",
     "nz_mlp_forward", "nz_mlp_backward", "nz_mlp_adam", "nz_set_timing", "nz_last_batch_timing",
-    "nz_mlp_loss", "nz_smax_window", "nz_convolve_window", "nz_last_batch_job_stats", "nz_last_batch_cc_timing",
+    "nz_mlp_loss", "nz_smax_window", "nz_convolve_window", "nz_sweep_batch_static", "nz_static_scratch_bytes",
+    "nz_last_batch_job_stats", "nz_last_batch_cc_timing",
     "nz_mlp_size_stats", "nz_mlp_features", "nz_prefill_target", "nz_prefill_plan",
 )
 
@@ -89,6 +90,10 @@ def lib():
     L.nz_batch_workspace_bytes.restype = ctypes.c_int
     L.nz_sweep_batch.argtypes = [P, i32, P, ctypes.c_size_t, P, P, P, P, P]
     L.nz_sweep_batch.restype = ctypes.c_int
+    L.nz_sweep_batch_static.argtypes = [P, i32, P, P, P, P, P]
+    L.nz_sweep_batch_static.restype = ctypes.c_int
+    L.nz_static_scratch_bytes.argtypes = []
+    L.nz_static_scratch_bytes.restype = ctypes.c_size_t
     L.nz_last_batch_stats.argtypes = [P]
     L.nz_last_batch_stats.restype = ctypes.c_int
     L.nz_last_batch_job_stats.argtypes = [P, P, i32]
@@ -234,6 +239,25 @@ def nz_sweep_batch(jobs, ws, nstar, mass=None, tune=None, stream=None):
                                 ctypes.c_void_p(mass.data_ptr()) if mass is not None else None,
                                 _np_ptr(back), ctypes.byref(t) if t is not None else None, _stream_ptr(stream)))
     return back[:n]
+
+
+def nz_sweep_batch_static(jobs, nstar, mass=None, tune=None, stream=None):
+    """nz_sweep_batch inside the library's own device buffer (no allocation).
+    nstar, mass are torch CUDA int32 tensors.  Returns the per-job backoff
+    counts as a numpy array."""
+    arr, n = make_jobs(jobs)
+    t = make_tuning(tune)
+    back = np.zeros(max(n, 1), dtype=np.int32)
+    _check(lib().nz_sweep_batch_static(ctypes.cast(arr, ctypes.c_void_p), n,
+                                       ctypes.c_void_p(nstar.data_ptr()) if nstar is not None else None,
+                                       ctypes.c_void_p(mass.data_ptr()) if mass is not None else None,
+                                       _np_ptr(back), ctypes.byref(t) if t is not None else None,
+                                       _stream_ptr(stream)))
+    return back[:n]
+
+
+def nz_static_scratch_bytes() -> int:
+    return int(lib().nz_static_scratch_bytes())
 
 
 def nz_last_batch_stats() -> dict:

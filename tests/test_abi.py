@@ -170,6 +170,26 @@ def test_split_needs_256_samples_in_each_group(monkeypatch):
     assert s == o
 
 
+def test_static_batch_rejects_oversized_samples_before_any_device_call():
+    """The no-allocation batch entry point checks, on the host, that one sample
+    of every job fits its fixed buffer: L = 40 (4 x 40^5 bytes of parents
+    alone) is refused with NZ_EWORKSPACE; L = 24 fits and goes on to the
+    argument check (a NULL n* output here)."""
+    import ctypes
+
+    assert nz.nz_static_scratch_bytes() == 256 << 20
+    arr, n = nz.make_jobs([dict(L=40, zone_mask=1, seed=1, nsamples=1)])
+    rc = nz.lib().nz_sweep_batch_static(ctypes.cast(arr, ctypes.c_void_p), n, None, None, None, None, None)
+    assert rc == nz.NZ_EWORKSPACE
+    assert b"needs" in nz.lib().nz_last_error()
+    arr, n = nz.make_jobs([dict(L=24, zone_mask=1, seed=1, nsamples=1)])
+    rc = nz.lib().nz_sweep_batch_static(ctypes.cast(arr, ctypes.c_void_p), n, None, None, None, None, None)
+    assert rc == nz.NZ_EINVAL
+    arr, n = nz.make_jobs([dict(L=4, zone_mask=0, seed=1, nsamples=1)])
+    rc = nz.lib().nz_sweep_batch_static(ctypes.cast(arr, ctypes.c_void_p), n, None, None, None, None, None)
+    assert rc == nz.NZ_EINVAL
+
+
 def test_batch_rejects_a_workspace_below_one_sample():
     """nz_sweep_batch refuses a workspace that cannot hold one sample with
     NZ_EWORKSPACE and a message, before any launch."""
