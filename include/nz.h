@@ -59,7 +59,7 @@ extern "C" {
 const char *nz_last_error(void);
 
 /* ABI version of this header. */
-#define NZ_ABI_VERSION 1
+#define NZ_ABI_VERSION 2
 int nz_abi_version(void);
 
 /* Number of sites z = |D(zone_mask)| of a neighbourhood (eq. (7)); -1 when
@@ -173,6 +173,9 @@ typedef struct {
  *                   skips loads of all-empty words.  1: on; 2: off; 0: on when
  *                   the chunk has at least 2 samples per compute unit (with
  *                   fewer resident waves the extra LDS read is not repaid).
+ *   split_z         when a batch runs as two groups side by side (see
+ *                   nz_sweep_batch), jobs with z <= split_z form the first
+ *                   group and the rest the second (10..892; 0: 64).
  */
 typedef struct {
     int32_t residency;
@@ -181,6 +184,7 @@ typedef struct {
     int32_t bucket_log2;
     int32_t sweep_mode;
     int32_t summary;
+    int32_t split_z;
 } nz_tuning;
 
 /* Device workspace bytes that lets nz_sweep_batch run the jobs with all their
@@ -201,9 +205,10 @@ int nz_batch_workspace_bytes(const nz_job *jobs, int32_t njobs, const nz_tuning 
  *   tune           may be NULL;  stream  hipStream_t (NULL: default stream).
  * Returns after the results are in d_nstar / d_mass (the call synchronises the
  * stream, because samples whose key band or bucket ran short are redone).
- * A batch with at least 256 samples of narrow neighbourhoods (z <= 64) and 256
- * of wider ones runs the two groups side by side when the workspace holds both
- * resident (nz_batch_workspace_bytes sizes it so): the wider group on a second
+ * A batch with at least 256 samples of narrow neighbourhoods (z <= 64, or
+ * z <= tune->split_z) and 256 of wider ones runs the two groups side by side
+ * when the workspace holds both resident (nz_batch_workspace_bytes sizes it
+ * so): the wider group on a second
  * host thread and a library-owned stream that first waits for the work already
  * queued on `stream`.  Results, backoff counts and statistics are the same as
  * for one group; the environment variable NZ_DEBUG_NO_SPLIT keeps one group.

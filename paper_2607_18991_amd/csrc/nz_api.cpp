@@ -379,6 +379,7 @@ struct Tune {
     int dcap = 64;
     int sweep_mode = 0;
     int summary = 0;
+    int split_z = 0;     // widest neighbourhood of the first of two groups side by side (0: kSplitZ)
     // keys launch: one workgroup per block of sites (false), or half as many
     // workgroups as the CUs hold at once, each looping over blocks (true)
     bool keys_resident = false;
@@ -415,6 +416,9 @@ int read_tune(const nz_tuning *t, Tune &out)
     out.sweep_mode = t->sweep_mode;
     if (t->summary < 0 || t->summary > 2) return fail(NZ_EINVAL, "tuning: summary %d outside [0, 2]", t->summary);
     out.summary = t->summary;
+    if (t->split_z != 0 && (t->split_z < 10 || t->split_z > 892))
+        return fail(NZ_EINVAL, "tuning: split_z %d outside [10, 892]", t->split_z);
+    out.split_z = t->split_z;
     out.residency = t->residency;
     out.wg_waves = t->wg_waves;
     out.waves_per_simd = t->waves_per_simd;
@@ -1105,7 +1109,7 @@ bool split_groups(const nz_job *jobs, int32_t njobs, const Tune &tune, SplitPlan
     if (getenv("NZ_DEBUG_NO_SPLIT")) return false;
     int64_t o = 0, count[2] = {0, 0};
     for (int j = 0; j < njobs; ++j) {
-        const int g = coordination(jobs[j].zone_mask) <= kSplitZ ? 0 : 1;
+        const int g = coordination(jobs[j].zone_mask) <= (tune.split_z ? tune.split_z : kSplitZ) ? 0 : 1;
         if (jobs[j].nsamples > 0) {
             sp.job[g].push_back(jobs[j]);
             sp.index[g].push_back(j);

@@ -48,7 +48,7 @@ class NzJob(ctypes.Structure):
 class NzTuning(ctypes.Structure):
     _fields_ = [("residency", ctypes.c_int32), ("wg_waves", ctypes.c_int32),
                 ("waves_per_simd", ctypes.c_int32), ("bucket_log2", ctypes.c_int32),
-                ("sweep_mode", ctypes.c_int32), ("summary", ctypes.c_int32)]
+                ("sweep_mode", ctypes.c_int32), ("summary", ctypes.c_int32), ("split_z", ctypes.c_int32)]
 
 
 class NzError(RuntimeError):
@@ -216,6 +216,7 @@ def make_tuning(tune) -> NzTuning | None:
     t.bucket_log2 = int(tune.get("bucket_log2", 0))
     t.sweep_mode = int(tune.get("sweep_mode", 0))
     t.summary = int(tune.get("summary", 0))
+    t.split_z = int(tune.get("split_z", 0))
     return t
 
 

@@ -25,7 +25,7 @@ def test_exports_every_declared_symbol():
     for n in names:
         assert hasattr(lib, n), n
     assert set(names) == set(nz.EXPORTS)
-    assert nz.nz_abi_version() == 1
+    assert nz.nz_abi_version() == 2
 
 
 def test_coordination_numbers(nzo):

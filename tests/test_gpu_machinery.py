@@ -226,3 +226,29 @@ def test_empty_inputs():
     torch.cuda.synchronize()
     assert (back == 0).all()
     assert (dn.cpu() == -7).all() and (dm.cpu() == -7).all()
+
+
+def test_shared_seed_jobs_mixed_members():
+    """Jobs that share seed, sample indices and L (the same occupation orders):
+    different prefill depths, a plain job, the same job twice, a job whose
+    prefill spans and backs off, sample ranges that only partly overlap, in a
+    chunked workspace and whole; every output equals the oracle's."""
+    from paper_2607_18991_amd import nz
+
+    L = 8
+    jobs = [dict(L=L, zone_mask=0x01, seed=91, nsamples=40, n0=4000, backoff=800),
+            dict(L=L, zone_mask=0x01, seed=91, nsamples=40),                          # plain, same keys
+            dict(L=L, zone_mask=0x01, seed=91, nsamples=40, n0=4000, backoff=800),   # the first job again
+            dict(L=L, zone_mask=0x7F, seed=91, nsamples=40, n0=40, backoff=20),
+            dict(L=L, zone_mask=0x7F, seed=91, nsamples=40, n0=L**5 - 1, backoff=L**5 // 2),  # spans: backs off
+            dict(L=L, zone_mask=0x0C, seed=91, sample0=25, nsamples=30, n0=300, backoff=100),
+            dict(L=6, zone_mask=0x01, seed=91, nsamples=20),                         # other size: its own groups
+            dict(L=L, zone_mask=0x03, seed=92, nsamples=20, n0=800, backoff=200)]    # other seed
+    want = oracle_batch(jobs)
+    gn, gm, back, _ = run_batch(jobs)
+    assert_same(jobs, gn, gm, *want)
+    assert back[4] >= 40
+    one = nz.nz_batch_workspace_bytes([dict(L=L, zone_mask=0x7F, seed=91, nsamples=1)])
+    gn, gm, _, stats = run_batch(jobs, ws_bytes=12 * one)
+    assert stats["chunks"] > 2
+    assert_same(jobs, gn, gm, *want)
