@@ -549,13 +549,49 @@ __device__ __forceinline__ bool xcd_slot(int32_t nlist, int32_t bx, int32_t &y, 
 // position of its bitset word (wpos) plus the set bits below t in that word.
 // The expand pass writes the lattice parent words the sweep reads.
 
-// Hook: one thread per prefilled site and its forward half of the offset
-// table (one of each +-d pair), eight neighbour words loaded at a time.
+// Hook: one lane per prefilled site and its forward half of the offset table
+// (one of each +-d pair), eight neighbour words loaded at a time.  The edges a
+// wave finds (site, occupied neighbour) are not linked where they are found:
+// each offset slot has only a few lanes with an occupied neighbour, so linking
+// slot by slot would run one round of dependent finds per slot with most lanes
+// idle.  They are appended to a per-wave edge buffer in LDS instead, and the
+// buffer is linked 64 edges at a time, every lane with an edge of its own.
 constexpr int HOOK_UNROLL = 8;
+// edges buffered per wave: one chunk of HOOK_UNROLL slots adds at most
+// 64 * HOOK_UNROLL, and the buffer is emptied whenever it holds 64 or more
+constexpr int HOOK_EBUF = 64 * (HOOK_UNROLL + 1);
 
 // Summary words a hook workgroup stages in LDS (the host sizes summaries to at
 // most 1025 words).
 constexpr int32_t HOOK_SUM_MAX = 1025;
+
+// Links list positions a and b: CAS links go from the larger root to the
+// smaller, only onto an entry that is still a root, retried from the parent the
+// CAS returns.
+__device__ __forceinline__ void cc_link(int32_t *par, int32_t a, int32_t b)
+{
+    int32_t u = cc_find(par, a);
+    int32_t v = cc_find(par, b);
+    while (u != v) {
+        const int32_t hi = max(u, v), lo = min(u, v);
+        int32_t expected = hi;
+        if (__hip_atomic_compare_exchange_strong(&par[hi], &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
+                                                 __HIP_MEMORY_SCOPE_AGENT))
+            break;
+        // hi is no longer a root: go on from the parent the CAS returned
+        u = cc_find(par, u == hi ? expected : u);
+        v = cc_find(par, v == hi ? expected : v);
+    }
+}
+
+// The buffered edges 0 .. ne-1 of one wave, 64 at a time.
+__device__ __forceinline__ void hook_flush(int32_t *par, const int32_t *ei, const int32_t *ej, int32_t ne, uint32_t lane)
+{
+    for (int32_t e0 = 0; e0 < ne; e0 += 64) {
+        const int32_t e = e0 + static_cast<int32_t>(lane);
+        if (e < ne) cc_link(par, ld_w(&ei[e]), ld_w(&ej[e]));
+    }
+}
 
 // PER: periodic coordinates (compiled apart, so that the free-boundary hook
 // carries no wrap correction).
@@ -565,6 +601,8 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
                                                       uint8_t *__restrict__ ws, NzState *__restrict__ state)
 {
     __shared__ uint32_t hsum[HOOK_SUM_MAX];
+    __shared__ int32_t ebuf_i[4][HOOK_EBUF];
+    __shared__ int32_t ebuf_j[4][HOOK_EBUF];
     int32_t y, x;
     if (!xcd_slot(nlist, bx, y, x)) return;
     const int sid = list[y];
@@ -589,13 +627,21 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
     const uint32_t *wpos = reinterpret_cast<const uint32_t *>(ws + d.off_wpos);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
     const NzOffset *tab = tabs + d.tab;
-    for (int32_t i = x * 256 + static_cast<int32_t>(threadIdx.x); i < n0; i += bx * 256) {
-        const int32_t s = static_cast<int32_t>(prefix[i]);
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x >> 6;
+    int32_t *ei = ebuf_i[wave];
+    int32_t *ej = ebuf_j[wave];
+    // the wave's 64 sites per pass (wave-uniform loop; lanes past n0 idle)
+    for (int32_t ib = x * 256 + static_cast<int32_t>(wave) * 64; ib < n0; ib += bx * 256) {
+        const int32_t i = ib + static_cast<int32_t>(lane);
+        const bool act = i < n0;
+        const int32_t s = act ? static_cast<int32_t>(prefix[i]) : 0;
         const uint32_t pc = pack_coords(static_cast<uint32_t>(s), static_cast<uint32_t>(L), magic);
-        const uint32_t A = allowed_axis(pc & 63, L) | (allowed_axis((pc >> 6) & 63, L) << 5) |
-                           (allowed_axis((pc >> 12) & 63, L) << 10) | (allowed_axis((pc >> 18) & 63, L) << 15) |
-                           (allowed_axis(pc >> 24, L) << 20);
-        int32_t u = -1;   // the site's root (or an ancestor of it), found at the first edge
+        const uint32_t A = act ? (allowed_axis(pc & 63, L) | (allowed_axis((pc >> 6) & 63, L) << 5) |
+                                  (allowed_axis((pc >> 12) & 63, L) << 10) | (allowed_axis((pc >> 18) & 63, L) << 15) |
+                                  (allowed_axis(pc >> 24, L) << 20))
+                               : 0u;
+        int32_t ne = 0;   // edges in the buffer (wave-uniform)
         for (int32_t k0 = 0; k0 < zh; k0 += HOOK_UNROLL) {
             int32_t t[HOOK_UNROLL];
             uint32_t w[HOOK_UNROLL];
@@ -608,37 +654,45 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
                 const uint32_t out = o.code & ~A;
                 bool ok;
                 if constexpr (PER) {
-                    ok = (o.code & ~kCodeBits) == 0u;   // every offset wraps back in, padding aside
+                    ok = act && (o.code & ~kCodeBits) == 0u;   // every offset wraps back in, padding aside
                     t[q] = s + o.stride + (out ? wrap_fix(out, L) : 0);
                 } else {
-                    ok = out == 0u;
+                    ok = act && out == 0u;
                     t[q] = s + o.stride;
                 }
                 const uint32_t wi = static_cast<uint32_t>(t[q]) >> 5;
                 const bool maybe = !use_sum || ((hsum[(wi >> gs) >> 5] >> ((wi >> gs) & 31)) & 1u);
                 w[q] = ok && maybe ? occ[wi] : 0u;
             }
+            // list positions of the occupied neighbours: their words' first
+            // positions, loaded together, plus the set bits below them
+            uint32_t jw[HOOK_UNROLL];
+#pragma unroll
+            for (int q = 0; q < HOOK_UNROLL; ++q)
+                jw[q] = ((w[q] >> (t[q] & 31)) & 1u) ? wpos[static_cast<uint32_t>(t[q]) >> 5] : 0xFFFFFFFFu;
 #pragma unroll
             for (int q = 0; q < HOOK_UNROLL; ++q) {
-                const uint32_t below = w[q] & ((1u << (t[q] & 31)) - 1u);
-                if (!((w[q] >> (t[q] & 31)) & 1u)) continue;
-                const int32_t j = static_cast<int32_t>(wpos[static_cast<uint32_t>(t[q]) >> 5]) + __popc(below);
-                if (u < 0) u = cc_find(par, i);
-                int32_t v = cc_find(par, j);
-                while (u != v) {
-                    const int32_t hi = max(u, v), lo = min(u, v);
-                    int32_t expected = hi;
-                    if (__hip_atomic_compare_exchange_strong(&par[hi], &expected, lo, __ATOMIC_RELAXED, __ATOMIC_RELAXED,
-                                                             __HIP_MEMORY_SCOPE_AGENT)) {
-                        u = lo;   // the site's root is now lo
-                        break;
-                    }
-                    // hi is no longer a root: go on from the parent the CAS returned
-                    u = cc_find(par, u == hi ? expected : u);
-                    v = cc_find(par, v == hi ? expected : v);
+                const bool edge = jw[q] != 0xFFFFFFFFu;
+                const uint64_t mk = __ballot(edge);
+                if (edge) {
+                    const int32_t e = ne + static_cast<int32_t>(__builtin_amdgcn_mbcnt_hi(
+                                               static_cast<uint32_t>(mk >> 32),
+                                               __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(mk), 0u)));
+                    st_w(&ei[e], i);
+                    st_w(&ej[e], static_cast<int32_t>(jw[q] + static_cast<uint32_t>(__popc(w[q] & ((1u << (t[q] & 31)) - 1u)))));
                 }
+                ne += static_cast<int32_t>(__popcll(mk));
+            }
+            if (ne >= 64) {
+                __builtin_amdgcn_wave_barrier();
+                hook_flush(par, ei, ej, ne, lane);
+                __builtin_amdgcn_wave_barrier();
+                ne = 0;
             }
         }
+        __builtin_amdgcn_wave_barrier();
+        hook_flush(par, ei, ej, ne, lane);
+        __builtin_amdgcn_wave_barrier();
     }
 }
 
