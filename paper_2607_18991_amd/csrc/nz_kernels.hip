@@ -223,6 +223,91 @@ __device__ __forceinline__ void keys_bucket(const KeysCtx &c, uint64_t K, uint32
     }
 }
 
+// The iterations of one wave over a block: keys, the prefill and band masks,
+// the prefill ballots (lane it keeps iteration it's) and the band queue.
+// FULL: the block lies wholly inside the lattice (no site needs a range test);
+// BALL: the band reaches 2^64 (every key at or above T0 is in it).
+struct KeysIter {
+    const KeysCtx &c;
+    uint64_t *qk;
+    uint32_t *qs;
+    uint32_t N;
+    uint32_t wave_base;
+    uint32_t lane;
+    uint64_t band_end;
+    uint32_t seed_lo, seed_hi, smp_lo, smp_hi;
+};
+
+template <bool FULL, bool BALL>
+__device__ __forceinline__ void keys_iters(const KeysIter &k, uint32_t &be_lo, uint32_t &be_hi, uint32_t &bo_lo,
+                                           uint32_t &bo_hi, int &its, uint32_t &nq)
+{
+    const KeysCtx &c = k.c;
+    uint64_t *qk = k.qk;
+    uint32_t *qs = k.qs;
+    const uint32_t lane = k.lane, lane2 = 2u * k.lane;
+    for (int it = 0; it < KEYS_ITERS; ++it) {
+        const uint32_t wbase = k.wave_base + static_cast<uint32_t>(it) * (2 * KEYS_THREADS);   // (scalar)
+        if (wbase >= k.N) break;
+        its = it + 1;
+        uint64_t K0, K1;
+        site_key_pair(k.seed_lo, k.seed_hi, k.smp_lo, k.smp_hi, (wbase >> 1) + lane, K0, K1);
+        // lane masks of the compares (prefilled: key < T0; band: T0 <= key <
+        // band_end), combined on the scalar unit
+        const uint64_t vm0 = FULL ? ~0ull : __builtin_amdgcn_uicmp(wbase + lane2, k.N, kIcmpUlt);
+        const uint64_t vm1 = FULL ? ~0ull : __builtin_amdgcn_uicmp(wbase + lane2 + 1u, k.N, kIcmpUlt);
+        const uint64_t be = vm0 & __builtin_amdgcn_uicmpl(K0, c.T0, kIcmpUlt);
+        const uint64_t bo = vm1 & __builtin_amdgcn_uicmpl(K1, c.T0, kIcmpUlt);
+        const uint64_t qe = (vm0 & ~be) & (BALL ? ~0ull : __builtin_amdgcn_uicmpl(K0, k.band_end, kIcmpUlt));
+        const uint64_t qo = (vm1 & ~bo) & (BALL ? ~0ull : __builtin_amdgcn_uicmpl(K1, k.band_end, kIcmpUlt));
+        if (lane == static_cast<uint32_t>(it)) {
+            be_lo = static_cast<uint32_t>(be);
+            be_hi = static_cast<uint32_t>(be >> 32);
+            bo_lo = static_cast<uint32_t>(bo);
+            bo_hi = static_cast<uint32_t>(bo >> 32);
+        }
+        // band: queued, then bucketed in full waves
+        const uint32_t nqe = static_cast<uint32_t>(__popcll(qe));
+        if (qe) {
+            if (__builtin_amdgcn_inverse_ballot_w64(qe)) {
+                const uint32_t e = nq + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(qe >> 32),
+                                                                  __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(qe), 0u));
+                qk[e] = K0;
+                qs[e] = wbase + lane2;
+            }
+        }
+        if (qo) {
+            if (__builtin_amdgcn_inverse_ballot_w64(qo)) {
+                const uint32_t e = nq + nqe + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(qo >> 32),
+                                                                        __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(qo), 0u));
+                qk[e] = K1;
+                qs[e] = wbase + lane2 + 1u;
+            }
+        }
+        nq = __builtin_amdgcn_readfirstlane(nq + nqe + static_cast<uint32_t>(__popcll(qo)));
+        __builtin_amdgcn_wave_barrier();
+        if (nq >= 64u) {
+            uint32_t base = 0;
+            for (; base + 64u <= nq; base += 64u) keys_bucket(c, qk[base + lane], qs[base + lane]);
+            // move the remainder (< 64 entries) to the front
+            const uint32_t rest = nq - base;
+            uint64_t rk = 0;
+            uint32_t rs = 0;
+            if (lane < rest) {
+                rk = qk[base + lane];
+                rs = qs[base + lane];
+            }
+            __builtin_amdgcn_wave_barrier();
+            if (lane < rest) {
+                qk[lane] = rk;
+                qs[lane] = rs;
+            }
+            __builtin_amdgcn_wave_barrier();
+            nq = __builtin_amdgcn_readfirstlane(rest);
+        }
+    }
+}
+
 __device__ __forceinline__ void keys_block(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
                                            int32_t first, int32_t blocks_per_sample, uint8_t *__restrict__ ws,
                                            NzState *__restrict__ state, int32_t vblock)
@@ -273,67 +358,25 @@ __device__ __forceinline__ void keys_block(const NzSample *__restrict__ desc, co
     uint32_t *qs = bq_site[wave];
     uint32_t nq = 0;        // wave-uniform
     const uint32_t block_base = static_cast<uint32_t>(blk) * KEYS_SITES_PER_BLOCK;
+    // wave-uniform values held in scalar registers: the first site of the
+    // wave's first iteration, whether the block lies wholly inside the
+    // lattice (then no site needs a range test) and whether the band reaches
+    // 2^64
+    const uint32_t wave_base = __builtin_amdgcn_readfirstlane(block_base + 128u * wave);
+    const bool full = __builtin_amdgcn_readfirstlane(block_base + KEYS_SITES_PER_BLOCK <= N ? 1u : 0u) != 0u;
+    const bool ball = __builtin_amdgcn_readfirstlane(band_all ? 1u : 0u) != 0u;
     // even / odd prefill ballots of iteration it, held by lane it
     uint32_t be_lo = 0, be_hi = 0, bo_lo = 0, bo_hi = 0;
     int its = 0;            // iterations this wave ran (wave-uniform)
-    for (int it = 0; it < KEYS_ITERS; ++it) {
-        const uint32_t wbase = block_base + it * (2 * KEYS_THREADS) + 2u * (threadIdx.x & ~63u);
-        if (wbase >= N) break;
-        its = it + 1;
-        const uint32_t i0 = wbase + 2u * lane, i1 = i0 + 1u;
-        uint64_t K0, K1;
-        site_key_pair(seed_lo, seed_hi, smp_lo, smp_hi, i0 >> 1, K0, K1);
-        // lane masks of the compares (prefilled: key < T0; band: T0 <= key <
-        // band_end), combined on the scalar unit
-        const uint64_t vm0 = __builtin_amdgcn_uicmp(i0, N, kIcmpUlt);
-        const uint64_t vm1 = __builtin_amdgcn_uicmp(i1, N, kIcmpUlt);
-        const uint64_t be = vm0 & __builtin_amdgcn_uicmpl(K0, c.T0, kIcmpUlt);
-        const uint64_t bo = vm1 & __builtin_amdgcn_uicmpl(K1, c.T0, kIcmpUlt);
-        const uint64_t qe = (vm0 & ~be) & (band_all ? ~0ull : __builtin_amdgcn_uicmpl(K0, band_end, kIcmpUlt));
-        const uint64_t qo = (vm1 & ~bo) & (band_all ? ~0ull : __builtin_amdgcn_uicmpl(K1, band_end, kIcmpUlt));
-        const bool band0 = __builtin_amdgcn_inverse_ballot_w64(qe);
-        const bool band1 = __builtin_amdgcn_inverse_ballot_w64(qo);
-        if (lane == static_cast<uint32_t>(it)) {
-            be_lo = static_cast<uint32_t>(be);
-            be_hi = static_cast<uint32_t>(be >> 32);
-            bo_lo = static_cast<uint32_t>(bo);
-            bo_hi = static_cast<uint32_t>(bo >> 32);
-        }
-        // band: queued, then bucketed in full waves
-        const uint32_t nqe = static_cast<uint32_t>(__popcll(qe));
-        if (band0) {
-            const uint32_t e = nq + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(qe >> 32),
-                                                              __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(qe), 0u));
-            qk[e] = K0;
-            qs[e] = i0;
-        }
-        if (band1) {
-            const uint32_t e = nq + nqe + __builtin_amdgcn_mbcnt_hi(static_cast<uint32_t>(qo >> 32),
-                                                                    __builtin_amdgcn_mbcnt_lo(static_cast<uint32_t>(qo), 0u));
-            qk[e] = K1;
-            qs[e] = i1;
-        }
-        nq += nqe + static_cast<uint32_t>(__popcll(qo));
-        __builtin_amdgcn_wave_barrier();
-        if (nq >= 64u) {
-            uint32_t base = 0;
-            for (; base + 64u <= nq; base += 64u) keys_bucket(c, qk[base + lane], qs[base + lane]);
-            // move the remainder (< 64 entries) to the front
-            const uint32_t rest = nq - base;
-            uint64_t rk = 0;
-            uint32_t rs = 0;
-            if (lane < rest) {
-                rk = qk[base + lane];
-                rs = qs[base + lane];
-            }
-            __builtin_amdgcn_wave_barrier();
-            if (lane < rest) {
-                qk[lane] = rk;
-                qs[lane] = rs;
-            }
-            __builtin_amdgcn_wave_barrier();
-            nq = rest;
-        }
+    // the loop is compiled for each combination of the two wave-uniform
+    // choices, so that no iteration tests them
+    KeysIter ki{c, qk, qs, N, wave_base, lane, band_end, seed_lo, seed_hi, smp_lo, smp_hi};
+    if (full) {
+        if (ball) keys_iters<true, true>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+        else keys_iters<true, false>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+    } else {
+        if (ball) keys_iters<false, true>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+        else keys_iters<false, false>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
     }
     if (lane < nq) keys_bucket(c, qk[lane], qs[lane]);
     {
