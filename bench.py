@@ -318,14 +318,15 @@ def main():
 
     if args.autotune_out:
         table = autotune.load_table()
-        batches = [(f"L={L} x 7 compact x {S}, plain", learned.plan_band_only(model, jobs0)),
-                   (f"L={L} x 7 compact x {S}, learned", model.plan(jobs0))]
+        batches = [(f"L={L} x 7 compact x {S}, plain", learned.plan_band_only(model, jobs0), None),
+                   (f"L={L} x 7 compact x {S}, learned", model.plan(jobs0), lambda k: model.plan(jobs0, k_sigma=k))]
         if args.l24_samples > 0:
             j24 = base_jobs(24, args.l24_samples, masks24)
-            batches += [(f"L=24 x 27 masks x {args.l24_samples}, plain", learned.plan_band_only(model, j24)),
-                        (f"L=24 x 27 masks x {args.l24_samples}, learned", model.plan(j24))]
-        for name, jobs in batches:
-            e = autotune.tune_batch(jobs, log=lambda m: print(f"{name}: {m}", flush=True))
+            batches += [(f"L=24 x 27 masks x {args.l24_samples}, plain", learned.plan_band_only(model, j24), None),
+                        (f"L=24 x 27 masks x {args.l24_samples}, learned", model.plan(j24),
+                         lambda k: model.plan(j24, k_sigma=k))]
+        for name, jobs, replan in batches:
+            e = autotune.tune_batch(jobs, log=lambda m: print(f"{name}: {m}", flush=True), replan=replan)
             autotune.add_batch(table, jobs, e, name)
             print(f"{name}: best {e['tune']} {e['ms']} ms (default {e['default_ms']} ms)", flush=True)
         autotune.save_table(table, args.autotune_out)
@@ -336,7 +337,8 @@ def main():
         S24 = args.l24_samples
         res = {}
         for mode in (("plain", "learned") if args.mode == "both" else (args.mode,)):
-            mk = (lambda: learned.plan_band_only(model, j24)) if mode == "plain" else (lambda: model.plan(j24))
+            k24 = autotune.plan_for(model.plan(j24)).get("k_sigma", 3.0)
+            mk = (lambda: learned.plan_band_only(model, j24)) if mode == "plain" else (lambda: model.plan(j24, k_sigma=k24))
             r = run_mode(nz, torch, mk, args.steps, args.warmup, autotune.for_jobs(mk()) or None)
             res[mode] = (r, summarise(r, args.steps, S24, z))
         out = {"workload": f"L=24 (N={24**5}) x 27 masks x {S24}", "masks": masks24}
@@ -352,8 +354,10 @@ def main():
         plain = run_mode(nz, torch, lambda: learned.plan_band_only(model, jobs0), args.steps, args.warmup,
                          autotune.for_jobs(jp) or None)
     if args.mode in ("both", "learned"):
-        jl = model.plan(jobs0)
-        learn = run_mode(nz, torch, lambda: model.plan(jobs0), args.steps, args.warmup,
+        # the prefill depth the batch was tuned with (mean - 3 std by default)
+        k16 = autotune.plan_for(model.plan(jobs0)).get("k_sigma", 3.0)
+        jl = model.plan(jobs0, k_sigma=k16)
+        learn = run_mode(nz, torch, lambda: model.plan(jobs0, k_sigma=k16), args.steps, args.warmup,
                          autotune.for_jobs(jl) or None)
     if args.mode == "plain":
         learn = plain
@@ -412,9 +416,10 @@ def main():
         # the same comparison at L = 24 (7,962,624 sites): the 7 compact and 20
         # random neighbourhoods, one untimed and one timed step per mode
         j24 = base_jobs(24, args.l24_samples, masks24)
-        jp24, jl24 = learned.plan_band_only(model, j24), model.plan(j24)
+        k24 = autotune.plan_for(model.plan(j24)).get("k_sigma", 3.0)
+        jp24, jl24 = learned.plan_band_only(model, j24), model.plan(j24, k_sigma=k24)
         p24 = run_mode(nz, torch, lambda: learned.plan_band_only(model, j24), 1, 1, autotune.for_jobs(jp24) or None)
-        l24 = run_mode(nz, torch, lambda: model.plan(j24), 1, 1, autotune.for_jobs(jl24) or None)
+        l24 = run_mode(nz, torch, lambda: model.plan(j24, k_sigma=k24), 1, 1, autotune.for_jobs(jl24) or None)
         s24p, s24l = summarise(p24, 1, args.l24_samples, z), summarise(l24, 1, args.l24_samples, z)
         out["L24"] = {"samples_per_mask": args.l24_samples, "masks": masks24,
                       "per_mask": per_mask(24, args.l24_samples) if not args.no_per_mask else None,

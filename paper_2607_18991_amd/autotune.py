@@ -136,23 +136,52 @@ def batch_candidates():
             for mode in (0, 1, 2) for wps in (4, 8) for wg in (1, 4) for summary in (1, 2)]
 
 
-def tune_batch(jobs, reps: int = 2, log=None):
-    """Times the batch under every batch candidate; every candidate must
-    reproduce the default's outputs."""
+# widest neighbourhood of the first group when a batch runs as two groups
+SPLIT_Z = (64, 130, 170, 242, 340)
+# prefill depth: n0 = (mean - k std) N
+K_SIGMA = (3.0, 2.5, 2.0, 1.5)
+
+
+def tune_batch(jobs, reps: int = 2, log=None, replan=None):
+    """Times the batch under every batch candidate, then the best one under
+    every split of the batch into two groups, then (replan(k) given: the jobs
+    planned with prefill depth mean - k std) every prefill depth; every
+    candidate must reproduce the default's outputs."""
     base_ms, ref = _time_batch(jobs, None, reps)
     best = (base_ms, None)
     tried = []
-    for cand in batch_candidates():
-        ms, out = _time_batch(jobs, cand, reps)
+
+    def consider(cand, js, extra=None):
+        nonlocal best
+        ms, out = _time_batch(js, cand, reps)
         if not (out == ref).all():
-            raise RuntimeError(f"tuning {cand} changed the outputs of the batch")
-        tried.append(dict(tune=cand, ms=round(ms, 3)))
+            raise RuntimeError(f"tuning {cand} {extra} changed the outputs of the batch")
+        tried.append(dict(tune=cand, ms=round(ms, 3), **({"plan": extra} if extra else {})))
+        if log:
+            log(f"batch {cand} {extra or ''} {ms:.3f} ms")
+        return ms
+
+    for cand in batch_candidates():
+        ms = consider(cand, jobs)
         if ms < best[0]:
             best = (ms, cand)
-        if log:
-            log(f"batch {cand} {ms:.3f} ms")
-    return {"tune": best[1] or {}, "ms": round(best[0], 3), "default_ms": round(base_ms, 3), "tried": tried,
-            "samples": int(sum(int(j["nsamples"]) for j in jobs))}
+    for sz in SPLIT_Z:
+        cand = dict(best[1] or {}, split_z=sz)
+        ms = consider(cand, jobs)
+        if ms < best[0]:
+            best = (ms, cand)
+    plan = None
+    if replan is not None:
+        for k in K_SIGMA:
+            ms = consider(best[1], replan(k), {"k_sigma": k})
+            if ms < best[0]:
+                best = (ms, best[1])
+                plan = {"k_sigma": k}
+    entry = {"tune": best[1] or {}, "ms": round(best[0], 3), "default_ms": round(base_ms, 3), "tried": tried,
+             "samples": int(sum(int(j["nsamples"]) for j in jobs))}
+    if plan:
+        entry["plan"] = plan
+    return entry
 
 
 def add_batch(table, jobs, entry, name: str):
@@ -216,6 +245,14 @@ def for_jobs(jobs, table=None):
     if tune.get("residency") in (1, 3) and total > LDS_RESIDENT_MAX_SAMPLES:
         tune.update(residency=2, wg_waves=1)
     return tune
+
+
+def plan_for(jobs, table=None) -> dict:
+    """Planner settings ({'k_sigma': ...}) of the batch's own entry, if it was
+    tuned as a whole with them; {} otherwise."""
+    t = table or load_table()
+    e = t.get("batches", {}).get(signature(jobs)) if jobs else None
+    return dict(e.get("plan", {})) if e else {}
 
 
 def save_table(table, path: str = TABLE_PATH):

@@ -245,3 +245,4 @@ def test_prefill_planning_host_calls():
     assert jobs[0].get("n0") is None                           # the caller's dicts are not touched
     plain = nz.nz_prefill_plan(y, jobs, 0.0, 5.0, plain=True)
     assert all(j["n0"] == -1 for j in plain) and plain[0]["band_hi"] == out[0]["band_hi"]
+

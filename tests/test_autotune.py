@@ -84,3 +84,20 @@ def test_summary_choice_kept_only_for_batches_like_the_timed_one():
     hbm = [c for c in autotune.candidates(16) if c["residency"] == 2]
     assert {c["summary"] for c in hbm} == {1, 2}
     assert {c.get("summary") for c in autotune.batch_candidates()} == {1, 2}
+
+
+def test_batch_plan_and_split_candidates():
+    """A batch entry may carry the planner's prefill depth; the split
+    candidates are accepted by the library and change only the grouping."""
+    table = {"format": autotune.FORMAT, "entries": {}}
+    jobs = [dict(L=16, zone_mask=m, seed=1, nsamples=500, n0=1000) for m in (0x01, 0x7F)]
+    assert autotune.plan_for(jobs, table) == {}
+    autotune.add_batch(table, jobs, {"tune": {"residency": 2, "split_z": 130}, "plan": {"k_sigma": 2.0}}, "b")
+    assert autotune.plan_for(jobs, table) == {"k_sigma": 2.0}
+    assert autotune.for_jobs(jobs, table)["split_z"] == 130
+    assert autotune.plan_for([], table) == {}
+    for sz in autotune.SPLIT_Z:
+        assert nz.nz_batch_workspace_bytes(jobs, dict(split_z=sz)) > 0
+    with pytest.raises(nz.NzError):
+        nz.nz_batch_workspace_bytes(jobs, dict(split_z=5))
+    assert all(k > 0 for k in autotune.K_SIGMA)

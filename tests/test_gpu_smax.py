@@ -69,3 +69,21 @@ def test_periodic_smax_window_matches_oracle(L, mask, seed, ns, lo, hi, n0):
     assert (got.astype(np.int64) == want).all()
     free = oracle.smax_window(L, mask, seed, 0, ns, lo, hi)
     assert not (free == want).all()   # the boundaries do matter here
+
+
+@pytest.mark.parametrize("L,mask,p", [(28, 0x01, 0.14079633), (32, 0x7F, 0.001934)])
+def test_large_lattice_window_matches_oracle(L, mask, p):
+    """The d_f runs' largest lattices (L = 28 and 32: 17.2 M and 33.6 M sites),
+    periodic, with a bulk prefill below the window as fss.py runs them: the
+    window sums of two samples equal the oracle's serial sweep run past n*."""
+    import oracle
+    from paper_2607_18991_amd import nz
+
+    N = L**5
+    centre = int(p * N)
+    lo, hi = centre - 400, centre + 400
+    n0 = int(0.9 * lo)
+    got = nz.nz_smax_window(L, mask, 0xDF5 + L, 0, 2, lo, hi, n0=n0, boundary=nz.NZ_PERIODIC)
+    want = oracle.smax_window(L, mask, 0xDF5 + L, 0, 2, lo, hi, periodic=True)
+    assert (got.astype(np.int64) == want).all()
+    assert want[-1] >= want[0] > 0
