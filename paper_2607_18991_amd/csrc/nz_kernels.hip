@@ -171,16 +171,28 @@ __global__ __launch_bounds__(256) void nz_clear_kernel(const NzSample *__restric
 
 // ---------------------------------------------------------------------------
 // Keys, prefill occupancy and band bucketing.  A block covers
-// KEYS_THREADS * 2 * KEYS_ITERS consecutive sites of one sample; per iteration
-// each wave takes 128 consecutive sites, lane l the pair (2l, 2l + 1) that
-// shares one Philox block, so two ballots yield four bitset words.  Lane `it`
-// keeps iteration it's ballots; after the loop lane l builds word l & 3 of
-// iteration l >> 2, so the bit interleave runs once for all of a wave's words.
+// KEYS_THREADS * 2 * KEYS_ITERS consecutive sites of one sample, wave w the
+// KEYS_WAVE_SITES sites from w * KEYS_WAVE_SITES; per iteration a wave takes
+// 128 consecutive sites, lane l the pair (2l, 2l + 1) that shares one Philox
+// block, so two ballots yield four bitset words.  Lane `it` keeps iteration
+// it's ballots; after the loop lane l builds word l & 3 of iteration 16 g +
+// l / 4 for every group g of 16 iterations, so the bit interleave runs once for
+// all of a wave's words.  A wave's fixed costs (its sample's descriptor, the
+// list atomic, the scans) are paid once per KEYS_WAVE_SITES sites: with 1024,
+// 2048, 4096 and 8192 sites per wave the kernel alone took 2.99, 1.97, 1.77
+// and 1.71 ms for 2000 samples of L = 16, zones 1-7, and 6.72, 4.58, 3.43 and
+// 2.88 ms for zone 1.
 
 constexpr int KEYS_THREADS = 256;
-constexpr int KEYS_ITERS = 8;
+#ifndef NZ_KEYS_ITERS
+#define NZ_KEYS_ITERS 64
+#endif
+constexpr int KEYS_ITERS = NZ_KEYS_ITERS;
+constexpr int KEYS_WAVE_SITES = 128 * KEYS_ITERS;
+constexpr int KEYS_GROUPS = KEYS_ITERS / 16;   // groups of 64 bitset words in a wave's range
 constexpr int KEYS_SITES_PER_BLOCK = KEYS_THREADS * 2 * KEYS_ITERS;
-static_assert(4 * KEYS_ITERS <= 64, "one lane per bitset word of a wave's iterations");
+static_assert(KEYS_ITERS % 16 == 0 && KEYS_ITERS <= 64, "whole 64-word groups; lane it keeps iteration it");
+static_assert(KEYS_SITES_PER_BLOCK == (KEYS_THREADS / 64) * KEYS_WAVE_SITES, "waves tile the block");
 
 // Predicate code of an unsigned less-than for the lane-mask compare builtins.
 constexpr int kIcmpUlt = 36;
@@ -247,7 +259,7 @@ __device__ __forceinline__ void keys_iters(const KeysIter &k, uint32_t &be_lo, u
     uint32_t *qs = k.qs;
     const uint32_t lane = k.lane, lane2 = 2u * k.lane;
     for (int it = 0; it < KEYS_ITERS; ++it) {
-        const uint32_t wbase = k.wave_base + static_cast<uint32_t>(it) * (2 * KEYS_THREADS);   // (scalar)
+        const uint32_t wbase = k.wave_base + static_cast<uint32_t>(it) * 128u;   // (scalar)
         if (wbase >= k.N) break;
         its = it + 1;
         uint64_t K0, K1;
@@ -312,15 +324,12 @@ __device__ __forceinline__ void keys_block(const NzSample *__restrict__ desc, co
                                            int32_t first, int32_t blocks_per_sample, uint8_t *__restrict__ ws,
                                            NzState *__restrict__ state, int32_t vblock)
 {
-    // The prefilled sites of this block are appended to the sample's list in
-    // site order, with one global atomic per block: their bitset words are kept
-    // in LDS, scanned, and every word's list position is stored, so that a
+    // Every wave works alone on its own KEYS_WAVE_SITES consecutive sites: no
+    // workgroup barrier, so a wave that waits for its list atomic or its
+    // sample's descriptor leaves the SIMD to the others.  The wave's prefilled
+    // sites are appended to the sample's list in site order with one global
+    // atomic, and every bitset word's list position is stored, so that a
     // site's list position is that of its word plus the set bits below it.
-    constexpr uint32_t kWords = KEYS_SITES_PER_BLOCK / 32;
-    __shared__ uint32_t pre_words[kWords];
-    __shared__ uint32_t pre_excl[kWords];
-    __shared__ uint32_t pre_tot[2];
-    __shared__ uint32_t pre_base;
     __shared__ uint64_t bq_key[KEYS_THREADS / 64][KEYS_BQ];
     __shared__ uint32_t bq_site[KEYS_THREADS / 64][KEYS_BQ];
     const int which = vblock / blocks_per_sample;
@@ -328,6 +337,13 @@ __device__ __forceinline__ void keys_block(const NzSample *__restrict__ desc, co
     const int blk = vblock % blocks_per_sample;
     const NzSample &d = desc[sid];
     const uint32_t N = static_cast<uint32_t>(d.N);
+    const uint32_t lane = lane_id();
+    const uint32_t wave = threadIdx.x >> 6;
+    // the first site of the wave's range (a multiple of 2048, so its bitset
+    // words start on a 64-word boundary)
+    const uint32_t wave_base =
+        __builtin_amdgcn_readfirstlane(static_cast<uint32_t>(blk) * KEYS_SITES_PER_BLOCK + KEYS_WAVE_SITES * wave);
+    if (wave_base >= N) return;   // wave-uniform
     const uint32_t seed_lo = static_cast<uint32_t>(d.seed), seed_hi = static_cast<uint32_t>(d.seed >> 32);
     const uint32_t smp_lo = static_cast<uint32_t>(d.sample), smp_hi = static_cast<uint32_t>(d.sample >> 32);
     const uint32_t occ_words = ((N + 63u) >> 6) << 1;   // padded to whole 64-site words
@@ -345,25 +361,18 @@ __device__ __forceinline__ void keys_block(const NzSample *__restrict__ desc, co
     c.counts = reinterpret_cast<uint32_t *>(ws + d.off_counts);
     uint32_t *occ = reinterpret_cast<uint32_t *>(ws + d.off_occ);
     uint32_t *prefix = reinterpret_cast<uint32_t *>(ws + d.off_prefix);
-    if (threadIdx.x < kWords) pre_words[threadIdx.x] = 0u;
-    __syncthreads();
     // keys in [T0, band_end) fall into the band (band_end saturates at 2^64)
     const uint64_t span = c.nb << c.shift;
     const bool band_all = c.shift >= 64 || (span >> c.shift) != c.nb || c.T0 + span < c.T0;
     const uint64_t band_end = c.T0 + span;
 
-    const uint32_t lane = lane_id();
-    const uint32_t wave = threadIdx.x >> 6;
     uint64_t *qk = bq_key[wave];
     uint32_t *qs = bq_site[wave];
     uint32_t nq = 0;        // wave-uniform
-    const uint32_t block_base = static_cast<uint32_t>(blk) * KEYS_SITES_PER_BLOCK;
-    // wave-uniform values held in scalar registers: the first site of the
-    // wave's first iteration, whether the block lies wholly inside the
-    // lattice (then no site needs a range test) and whether the band reaches
-    // 2^64
-    const uint32_t wave_base = __builtin_amdgcn_readfirstlane(block_base + 128u * wave);
-    const bool full = __builtin_amdgcn_readfirstlane(block_base + KEYS_SITES_PER_BLOCK <= N ? 1u : 0u) != 0u;
+    // wave-uniform choices held in scalar registers: whether the wave's range
+    // lies wholly inside the lattice (then no site needs a range test) and
+    // whether the band reaches 2^64
+    const bool full = __builtin_amdgcn_readfirstlane(wave_base + KEYS_WAVE_SITES <= N ? 1u : 0u) != 0u;
     const bool ball = __builtin_amdgcn_readfirstlane(band_all ? 1u : 0u) != 0u;
     // even / odd prefill ballots of iteration it, held by lane it
     uint32_t be_lo = 0, be_hi = 0, bo_lo = 0, bo_hi = 0;
@@ -379,12 +388,19 @@ __device__ __forceinline__ void keys_block(const NzSample *__restrict__ desc, co
         else keys_iters<false, false>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
     }
     if (lane < nq) keys_bucket(c, qk[lane], qs[lane]);
-    {
-        // Word q of iteration it (sites wbase .. wbase + 127 of that iteration)
-        // interleaves bits 16q .. 16q + 15 of the even and odd ballots; lane
-        // 4 it + q builds it.  Words past the padded bitset are not stored.
-        const int src = static_cast<int>(lane >> 2);
-        const uint32_t q = lane & 3u;
+
+    // Word q of iteration it (sites wave_base + 128 it .. + 127) interleaves
+    // bits 16q .. 16q + 15 of the even and odd ballots.  The range's words come
+    // in groups of 64, one word per lane: lane l of group g builds word 64 g + l,
+    // that of iteration 16 g + l / 4.  Words of iterations that did not run are
+    // zero; words past the padded bitset are not stored.
+    const uint32_t q = lane & 3u;
+    const uint32_t w0 = wave_base >> 5;
+    uint32_t word[KEYS_GROUPS];
+    bool mine[KEYS_GROUPS];
+#pragma unroll
+    for (int g = 0; g < KEYS_GROUPS; ++g) {
+        const int src = 16 * g + static_cast<int>(lane >> 2);
         const uint32_t elo = static_cast<uint32_t>(__shfl(static_cast<int>(be_lo), src));
         const uint32_t ehi = static_cast<uint32_t>(__shfl(static_cast<int>(be_hi), src));
         const uint32_t olo = static_cast<uint32_t>(__shfl(static_cast<int>(bo_lo), src));
@@ -392,77 +408,78 @@ __device__ __forceinline__ void keys_block(const NzSample *__restrict__ desc, co
         const uint32_t sh = 16u * (q & 1u);
         const uint32_t e16 = ((q < 2u ? elo : ehi) >> sh) & 0xFFFFu;
         const uint32_t o16 = ((q < 2u ? olo : ohi) >> sh) & 0xFFFFu;
-        const uint32_t word = spread_even(e16) | (spread_even(o16) << 1);
-        const uint32_t widx = (block_base >> 5) + static_cast<uint32_t>(src) * (2u * KEYS_THREADS / 32u) + 4u * wave + q;
-        if (src < its) {
-            if (widx < occ_words) occ[widx] = word;
-            // the block's prefilled words, in site order (chunk it * 4 + wave)
-            pre_words[(static_cast<uint32_t>(src) * 4u + wave) * 4u + q] = word;
-        }
+        mine[g] = src < its;
+        word[g] = mine[g] ? (spread_even(e16) | (spread_even(o16) << 1)) : 0u;
+        const uint32_t w = w0 + 64u * static_cast<uint32_t>(g) + lane;
+        if (mine[g] && w < occ_words) occ[w] = word[g];
     }
-    if (d.T0 == 0) return;   // plain sample: nothing prefilled (uniform over the block)
-    __syncthreads();
-    // exclusive scan of the 128 word counts (waves 0 and 1, one word per lane)
-    uint32_t wc = 0, incl = 0;
-    if (threadIdx.x < kWords) {
-        wc = static_cast<uint32_t>(__popc(pre_words[threadIdx.x]));
-        incl = wc;
+    if (d.T0 == 0) return;   // plain sample: nothing prefilled (uniform over the grid)
+
+    // summary bits of the range's non-empty words, and the exclusive scan of
+    // the word counts of every group
+    uint32_t *sum = reinterpret_cast<uint32_t *>(ws + d.off_sum);
+    const uint32_t gs = static_cast<uint32_t>(d.sum_shift);
+    uint32_t wc[KEYS_GROUPS], excl[KEYS_GROUPS], cnt[KEYS_GROUPS];
+    uint32_t total = 0;
+#pragma unroll
+    for (int g = 0; g < KEYS_GROUPS; ++g) {
+        wc[g] = static_cast<uint32_t>(__popc(word[g]));
+        const uint32_t wg0 = w0 + 64u * static_cast<uint32_t>(g);   // a multiple of 64
+        if (d.sum_words > 0) {
+            const uint64_t nzw = __ballot(wc[g] != 0u);
+            if (gs == 0u) {
+                // one bit per word: the group's bits fill two whole words
+                const uint32_t half = lane < 2u ? static_cast<uint32_t>(nzw >> (32u * lane)) : 0u;
+                if (half) atomicOr(&sum[(wg0 >> 5) + lane], half);
+            } else if (lane == 0u && nzw) {
+                // bit j of v: any of the 2^gs words j << gs .. of the group (1 <=
+                // gs <= 4); k is a multiple of 64 >> gs, so v fits in one word
+                const uint32_t span_bits = 64u >> gs;
+                const uint64_t grp = (1ull << (1u << gs)) - 1ull;
+                uint32_t v = 0u;
+                for (uint32_t j = 0; j < span_bits; ++j)
+                    if ((nzw >> (j << gs)) & grp) v |= 1u << j;
+                const uint32_t k = wg0 >> gs;
+                atomicOr(&sum[k >> 5], v << (k & 31u));
+            }
+        }
+        uint32_t incl = wc[g];
 #pragma unroll
         for (int o = 1; o < 64; o <<= 1) {
-            const uint32_t v = __shfl_up(incl, o);
+            const uint32_t v = static_cast<uint32_t>(__shfl_up(static_cast<int>(incl), o));
             if (lane >= static_cast<uint32_t>(o)) incl += v;
         }
-        if (lane == 63u) pre_tot[wave] = incl;
+        excl[g] = incl - wc[g];
+        cnt[g] = __builtin_amdgcn_readlane(incl, 63);
+        total += cnt[g];
     }
-    // summary bits of the block's non-empty words (one or two atomics per wave)
-    if (threadIdx.x < kWords && d.sum_words > 0) {
-        const uint64_t nz = __ballot(wc != 0u);
-        const uint32_t gs = static_cast<uint32_t>(d.sum_shift);
-        const uint32_t wfirst = (block_base >> 5) + wave * 64u;   // a multiple of 64
-        uint32_t *sum = reinterpret_cast<uint32_t *>(ws + d.off_sum);
-        if (gs == 0u) {
-            const uint32_t half = lane < 2u ? static_cast<uint32_t>(nz >> (32u * lane)) : 0u;
-            if (half) atomicOr(&sum[(wfirst >> 5) + lane], half);
-        } else if (lane == 0u && nz) {
-            // bit j of v: any of the 2^gs words j << gs .. of this wave (gs <= 4)
-            const uint32_t span = 64u >> gs;
-            uint32_t v = 0u;
-            for (uint32_t j = 0; j < span; ++j)
-                if ((nz >> (j << gs)) & ((1ull << (1u << gs)) - 1ull)) v |= 1u << j;
-            const uint32_t k = wfirst >> gs;
-            atomicOr(&sum[k >> 5], v << (k & 31));
-        }
-    }
-    __syncthreads();
-    const uint32_t cnt = pre_tot[0] + pre_tot[1];
-    if (cnt == 0) return;
-    if (threadIdx.x < kWords) pre_excl[threadIdx.x] = incl - wc + (wave == 1u ? pre_tot[0] : 0u);
-    if (threadIdx.x == 0) pre_base = atomicAdd(reinterpret_cast<uint32_t *>(&state[sid].n0), cnt);
-    __syncthreads();
-    const uint32_t base = pre_base;
+    if (total == 0u) return;   // wave-uniform
+    uint32_t got = 0u;
+    if (lane == 0u) got = atomicAdd(reinterpret_cast<uint32_t *>(&state[sid].n0), total);
+    uint32_t base = __builtin_amdgcn_readlane(got, 0);
+    uint32_t *wpos = reinterpret_cast<uint32_t *>(ws + d.off_wpos);
     const uint32_t cap = static_cast<uint32_t>(d.prefix_cap);
-    const uint32_t w0 = block_base >> 5;
-    if (!d.wrap && threadIdx.x < kWords && w0 + threadIdx.x < occ_words) {
-        uint32_t *wpos = reinterpret_cast<uint32_t *>(ws + d.off_wpos);
-        wpos[w0 + threadIdx.x] = base + pre_excl[threadIdx.x];
-    }
-    // the sites: two threads per word, 16 bits each, in bit order
-    const uint32_t k = threadIdx.x >> 1, h = threadIdx.x & 1u;
-    const uint32_t wv = pre_words[k];
-    uint32_t bits = (wv >> (16u * h)) & 0xFFFFu;
-    uint32_t pos = base + pre_excl[k] + (h ? static_cast<uint32_t>(__popc(wv & 0xFFFFu)) : 0u);
-    const uint32_t site0 = block_base + k * 32u + 16u * h;
     int32_t *parc = reinterpret_cast<int32_t *>(ws + d.off_parc);
-    while (bits) {
-        const uint32_t sidx = site0 + static_cast<uint32_t>(__builtin_ctz(bits));
-        bits &= bits - 1u;
-        if (pos < cap) {
-            prefix[pos] = sidx;
-            // parent = itself (periodic first-wrap: lattice entry, displacement 0)
-            if (d.wrap) reinterpret_cast<uint64_t *>(c.par)[sidx] = sidx;
-            else parc[pos] = static_cast<int32_t>(pos);
+#pragma unroll
+    for (int g = 0; g < KEYS_GROUPS; ++g) {
+        const uint32_t w = w0 + 64u * static_cast<uint32_t>(g) + lane;
+        uint32_t pos = base + excl[g];
+        if (!d.wrap && mine[g] && w < occ_words) wpos[w] = pos;
+        // the word's sites in bit order, one lane per word
+        uint32_t bits = word[g];
+        const uint32_t site0 = w << 5;
+        while (bits) {
+            const uint32_t sidx = site0 + static_cast<uint32_t>(__builtin_ctz(bits));
+            bits &= bits - 1u;
+            if (pos < cap) {
+                prefix[pos] = sidx;
+                // parent = itself (periodic first-wrap: lattice entry, displacement 0)
+                if (d.wrap) reinterpret_cast<uint64_t *>(c.par)[sidx] = sidx;
+                else parc[pos] = static_cast<int32_t>(pos);
+            }
+            ++pos;
         }
-        ++pos;
+        base += cnt[g];
     }
 }
 
@@ -475,7 +492,6 @@ __global__ __launch_bounds__(KEYS_THREADS) void nz_keys_kernel(const NzSample *_
 {
     for (int32_t vb = static_cast<int32_t>(blockIdx.x); vb < nblocks; vb += static_cast<int32_t>(gridDim.x)) {
         keys_block(desc, list, first, blocks_per_sample, ws, state, vb);
-        __syncthreads();   // the next block reuses the LDS
     }
 }
 
@@ -1147,15 +1163,8 @@ __device__ __forceinline__ void sweep_step(const SweepMem<RES> &m, uint32_t *lds
     int32_t lroot = s;
     uint32_t lword = NZ_ROOT | cur.fl | 1u;
     int D = 1;
-#pragma unroll
-    for (int c = 0; c < NCH; ++c) {
-        const int32_t t = cur.nbr(c, ostride, ocode, L);
-        const bool o = (cur.word[c] >> (t & 31)) & 1u;   // the word is 0 outside the lattice
-        uint64_t mk = __ballot(o);
-        if (!mk) continue;
-        int32_t root = 0;
-        uint32_t rw = 0;
-        if (o) sweep_find<RES>(m, lds, t, root, rw);
+    // Enter the roots found by the lanes of mk (root / rw) into the list.
+    auto enter = [&](uint64_t mk, int32_t root, uint32_t rw) {
         bool stale = false;   // a flush since these finds may have linked their roots
         while (mk) {
             const int l = __builtin_ctzll(mk);
@@ -1177,6 +1186,40 @@ __device__ __forceinline__ void sweep_step(const SweepMem<RES> &m, uint32_t *lds
             lroot = static_cast<int>(lane) == D ? rr : lroot;
             lword = static_cast<int>(lane) == D ? rrw : lword;
             ++D;
+        }
+    };
+    // Near the threshold a wide neighbourhood has a few occupied neighbours,
+    // rarely two on one lane: then every lane holds at most one and all the
+    // finds run at once instead of one offset chunk after another.
+    int32_t cand = -1;
+    bool two = false;
+#pragma unroll
+    for (int c = 0; c < NCH; ++c) {
+        const int32_t t = cur.nbr(c, ostride, ocode, L);
+        if ((cur.word[c] >> (t & 31)) & 1u) {   // the word is 0 outside the lattice
+            two = two || cand >= 0;
+            cand = t;
+        }
+    }
+    if (NCH == 1 || !__ballot(two)) {
+        const uint64_t mk = __ballot(cand >= 0);
+        if (mk) {
+            int32_t root = 0;
+            uint32_t rw = 0;
+            if (cand >= 0) sweep_find<RES>(m, lds, cand, root, rw);
+            enter(mk, root, rw);
+        }
+    } else {
+#pragma unroll
+        for (int c = 0; c < NCH; ++c) {
+            const int32_t t = cur.nbr(c, ostride, ocode, L);
+            const bool o = (cur.word[c] >> (t & 31)) & 1u;
+            const uint64_t mk = __ballot(o);
+            if (!mk) continue;
+            int32_t root = 0;
+            uint32_t rw = 0;
+            if (o) sweep_find<RES>(m, lds, t, root, rw);
+            enter(mk, root, rw);
         }
     }
     sweep_merge<RES>(m, lds, D, lroot, lword, total, flags);
