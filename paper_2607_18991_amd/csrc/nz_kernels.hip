@@ -616,9 +616,11 @@ __device__ __forceinline__ bool xcd_slot(int32_t nlist, int32_t bx, int32_t &y, 
 // idle.  They are appended to a per-wave edge buffer in LDS instead, and the
 // buffer is linked 64 edges at a time, every lane with an edge of its own.
 constexpr int HOOK_UNROLL = 8;
-// edges buffered per wave: one chunk of HOOK_UNROLL slots adds at most
-// 64 * HOOK_UNROLL, and the buffer is emptied whenever it holds 64 or more
-constexpr int HOOK_EBUF = 64 * (HOOK_UNROLL + 1);
+// edges buffered per wave: one offset slot adds at most 64, and the buffer is
+// emptied whenever it holds 64 or more (a small buffer leaves LDS for more
+// resident workgroups: this kernel is bound by the latency of its dependent
+// loads and atomics)
+constexpr int HOOK_EBUF = 128;
 
 // Summary words a hook workgroup stages in LDS (the host sizes summaries to at
 // most 1025 words).
@@ -741,12 +743,12 @@ __global__ __launch_bounds__(256) void nz_hook_kernel(const NzSample *__restrict
                     st_w(&ej[e], static_cast<int32_t>(jw[q] + static_cast<uint32_t>(__popc(w[q] & ((1u << (t[q] & 31)) - 1u)))));
                 }
                 ne += static_cast<int32_t>(__popcll(mk));
-            }
-            if (ne >= 64) {
-                __builtin_amdgcn_wave_barrier();
-                hook_flush(par, ei, ej, ne, lane);
-                __builtin_amdgcn_wave_barrier();
-                ne = 0;
+                if (ne >= 64) {
+                    __builtin_amdgcn_wave_barrier();
+                    hook_flush(par, ei, ej, ne, lane);
+                    __builtin_amdgcn_wave_barrier();
+                    ne = 0;
+                }
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -798,9 +800,9 @@ __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__rest
 }
 
 // Sizes and border flags of the prefilled clusters: members add themselves to
-// their root word.  The flag OR returns the previous word, so the member that
-// completes a root's pair of border flags sees it: the state already spans and
-// the sample backs off.
+// their root word.  No atomic here returns a value, so no wave waits on one; a
+// root that ends up with both border flags (the state already spans, and the
+// sample backs off) is found by the expand pass, which reads every root word.
 __global__ __launch_bounds__(256) void nz_accum_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
                                                        int32_t nlist, int32_t bx, uint8_t *__restrict__ ws,
                                                        NzState *__restrict__ state)
@@ -824,16 +826,16 @@ __global__ __launch_bounds__(256) void nz_accum_kernel(const NzSample *__restric
             uint32_t *root = reinterpret_cast<uint32_t *>(&par[r]);
             atomicAdd(root, 1u);
             const uint32_t fl = d.periodic ? 0u : border_flags(prefix[k], L, d.magic);
-            if (fl) {
-                const uint32_t old = atomicOr(root, fl);
-                if (((old | fl) & NZ_FLAGS) == NZ_FLAGS && !d.smax_mode) state[sid].status = NZ_ST_BACKOFF;
-            }
+            if (fl) (void)atomicOr(root, fl);
         }
     }
 }
 
 // Expand: the lattice parent word of every prefilled site, from the list
-// forest (a root keeps its root word, a member points at its root's site).
+// forest (a root keeps its root word, a member points at its root's site).  A
+// root word with both border flags means the prefilled state already spans:
+// the sample backs off (not in largest-cluster runs, which stop below the
+// window instead).
 __global__ __launch_bounds__(256) void nz_expand_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
                                                         int32_t nlist, int32_t bx, uint8_t *__restrict__ ws,
                                                         NzState *__restrict__ state)
@@ -847,10 +849,13 @@ __global__ __launch_bounds__(256) void nz_expand_kernel(const NzSample *__restri
     int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
     const int32_t *parc = reinterpret_cast<const int32_t *>(ws + d.off_parc);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
+    bool spans = false;
     for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
         const int32_t v = parc[k];
         par[prefix[k]] = v < 0 ? v : static_cast<int32_t>(prefix[v]);
+        spans = spans || (v < 0 && (static_cast<uint32_t>(v) & NZ_FLAGS) == NZ_FLAGS);
     }
+    if (spans && !d.smax_mode) state[sid].status = NZ_ST_BACKOFF;
 }
 
 // Largest cluster of the prefilled state (smax mode): every root word offers
