@@ -224,9 +224,12 @@ def keys_roofline(sites_step, keys_ms_step, prof):
     else:
         peak, basis = 256 * 64 * 2.4e9 / 34 / 1e9, "256 CUs x 64 lanes x 2.4 GHz / 34 operations per site"
     t, n = traffic_of(prof, ["nz::nz_keys_kernel"])
+    # the whole step's keys at the peak rate: the floor the keys set under
+    # ms_per_step
     return {"bound": "alu", "achieved": achieved, "peak": peak, "unit": "Gsites/s", "frac": achieved / peak,
             "traffic": t / n if t else None, "kernel": "nz_keys_kernel", "launches_per_step": n,
-            "kernel_ms": keys_ms_step / n if n else None, "peak_basis": basis}
+            "kernel_ms": keys_ms_step / n if n else None, "peak_basis": basis,
+            "floor_ms_per_step": sites_step / (peak * 1e9) * 1e3}
 
 
 def host_cpu():
@@ -319,12 +322,13 @@ def main():
     if args.autotune_out:
         table = autotune.load_table()
         batches = [(f"L={L} x 7 compact x {S}, plain", learned.plan_band_only(model, jobs0), None),
-                   (f"L={L} x 7 compact x {S}, learned", model.plan(jobs0), lambda k: model.plan(jobs0, k_sigma=k))]
+                   (f"L={L} x 7 compact x {S}, learned", model.plan(jobs0),
+                    lambda k, kw, sz: model.plan(jobs0, k_sigma=k, k_sigma_wide=kw, split_z=sz))]
         if args.l24_samples > 0:
             j24 = base_jobs(24, args.l24_samples, masks24)
             batches += [(f"L=24 x 27 masks x {args.l24_samples}, plain", learned.plan_band_only(model, j24), None),
                         (f"L=24 x 27 masks x {args.l24_samples}, learned", model.plan(j24),
-                         lambda k: model.plan(j24, k_sigma=k))]
+                         lambda k, kw, sz: model.plan(j24, k_sigma=k, k_sigma_wide=kw, split_z=sz))]
         for name, jobs, replan in batches:
             e = autotune.tune_batch(jobs, log=lambda m: print(f"{name}: {m}", flush=True), replan=replan)
             autotune.add_batch(table, jobs, e, name)
@@ -337,8 +341,8 @@ def main():
         S24 = args.l24_samples
         res = {}
         for mode in (("plain", "learned") if args.mode == "both" else (args.mode,)):
-            k24 = autotune.plan_for(model.plan(j24)).get("k_sigma", 3.0)
-            mk = (lambda: learned.plan_band_only(model, j24)) if mode == "plain" else (lambda: model.plan(j24, k_sigma=k24))
+            p24 = autotune.plan_for(model.plan(j24))
+            mk = (lambda: learned.plan_band_only(model, j24)) if mode == "plain" else (lambda: model.plan(j24, **p24))
             r = run_mode(nz, torch, mk, args.steps, args.warmup, autotune.for_jobs(mk()) or None)
             res[mode] = (r, summarise(r, args.steps, S24, z))
         out = {"workload": f"L=24 (N={24**5}) x 27 masks x {S24}", "masks": masks24}
@@ -355,9 +359,9 @@ def main():
                          autotune.for_jobs(jp) or None)
     if args.mode in ("both", "learned"):
         # the prefill depth the batch was tuned with (mean - 3 std by default)
-        k16 = autotune.plan_for(model.plan(jobs0)).get("k_sigma", 3.0)
-        jl = model.plan(jobs0, k_sigma=k16)
-        learn = run_mode(nz, torch, lambda: model.plan(jobs0, k_sigma=k16), args.steps, args.warmup,
+        p16 = autotune.plan_for(model.plan(jobs0))
+        jl = model.plan(jobs0, **p16)
+        learn = run_mode(nz, torch, lambda: model.plan(jobs0, **p16), args.steps, args.warmup,
                          autotune.for_jobs(jl) or None)
     if args.mode == "plain":
         learn = plain
@@ -416,10 +420,10 @@ def main():
         # the same comparison at L = 24 (7,962,624 sites): the 7 compact and 20
         # random neighbourhoods, one untimed and one timed step per mode
         j24 = base_jobs(24, args.l24_samples, masks24)
-        k24 = autotune.plan_for(model.plan(j24)).get("k_sigma", 3.0)
-        jp24, jl24 = learned.plan_band_only(model, j24), model.plan(j24, k_sigma=k24)
+        pl24 = autotune.plan_for(model.plan(j24))
+        jp24, jl24 = learned.plan_band_only(model, j24), model.plan(j24, **pl24)
         p24 = run_mode(nz, torch, lambda: learned.plan_band_only(model, j24), 1, 1, autotune.for_jobs(jp24) or None)
-        l24 = run_mode(nz, torch, lambda: model.plan(j24, k_sigma=k24), 1, 1, autotune.for_jobs(jl24) or None)
+        l24 = run_mode(nz, torch, lambda: model.plan(j24, **pl24), 1, 1, autotune.for_jobs(jl24) or None)
         s24p, s24l = summarise(p24, 1, args.l24_samples, z), summarise(l24, 1, args.l24_samples, z)
         out["L24"] = {"samples_per_mask": args.l24_samples, "masks": masks24,
                       "per_mask": per_mask(24, args.l24_samples) if not args.no_per_mask else None,

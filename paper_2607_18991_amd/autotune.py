@@ -144,9 +144,11 @@ K_SIGMA = (3.0, 2.5, 2.0, 1.5, 1.0)
 
 def tune_batch(jobs, reps: int = 2, log=None, replan=None):
     """Times the batch under every batch candidate, then the best one under
-    every split of the batch into two groups, then (replan(k) given: the jobs
-    planned with prefill depth mean - k std) every prefill depth; every
-    candidate must reproduce the default's outputs."""
+    every split of the batch into two groups, then (replan(k, k_wide, split_z)
+    given: the jobs planned with prefill depth mean - k std, and mean - k_wide
+    std for the jobs wider than split_z) every prefill depth for all jobs, and
+    then every depth for the wide jobs alone; every candidate must reproduce
+    the default's outputs."""
     base_ms, ref = _time_batch(jobs, None, reps)
     best = (base_ms, None)
     tried = []
@@ -173,10 +175,20 @@ def tune_batch(jobs, reps: int = 2, log=None, replan=None):
     plan = None
     if replan is not None:
         for k in K_SIGMA:
-            ms = consider(best[1], replan(k), {"k_sigma": k})
+            ms = consider(best[1], replan(k, None, None), {"k_sigma": k})
             if ms < best[0]:
                 best = (ms, best[1])
                 plan = {"k_sigma": k}
+        k0 = (plan or {}).get("k_sigma", 3.0)
+        sz = (best[1] or {}).get("split_z")
+        for kw in K_SIGMA:
+            if kw == k0:
+                continue
+            extra = {"k_sigma": k0, "k_sigma_wide": kw, "split_z": sz}
+            ms = consider(best[1], replan(k0, kw, sz), extra)
+            if ms < best[0]:
+                best = (ms, best[1])
+                plan = extra
     entry = {"tune": best[1] or {}, "ms": round(best[0], 3), "default_ms": round(base_ms, 3), "tried": tried,
              "samples": int(sum(int(j["nsamples"]) for j in jobs))}
     if plan:
@@ -248,11 +260,13 @@ def for_jobs(jobs, table=None):
 
 
 def plan_for(jobs, table=None) -> dict:
-    """Planner settings ({'k_sigma': ...}) of the batch's own entry, if it was
-    tuned as a whole with them; {} otherwise."""
+    """Planner settings ({'k_sigma': ..., and possibly 'k_sigma_wide' and
+    'split_z'}) of the batch's own entry, if it was tuned as a whole with
+    them; {} otherwise.  They are the keyword arguments of
+    learned.PrefillModel.plan."""
     t = table or load_table()
     e = t.get("batches", {}).get(signature(jobs)) if jobs else None
-    return dict(e.get("plan", {})) if e else {}
+    return {k: v for k, v in e.get("plan", {}).items() if v is not None} if e else {}
 
 
 def save_table(table, path: str = TABLE_PATH):

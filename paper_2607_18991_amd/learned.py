@@ -1,7 +1,7 @@
 """Learned prefill: a small MLP predicts, for a lattice (zone mask, L), the mean
 and the spread of n*/N; each sample then starts its Newman-Ziff sweep (Sec. II.B)
-from a bulk state with n0 = (mean - 3 std) N sites already occupied and
-labelled.  The prediction only moves work between the bulk and the sequential
+from a bulk state with n0 = (mean - k std) N sites already occupied and
+labelled (k = 3 unless a tuned batch says otherwise).  The prediction only moves work between the bulk and the sequential
 phase: a sample whose bulk state already spans backs off, so n* and the mass
 never depend on it.
 
@@ -107,11 +107,37 @@ class PrefillModel:
         out = self.forward(masks, Ls, stream).astype(np.float64)
         return np.exp(out[:, 0]), np.exp(out[:, 1])
 
-    def plan(self, jobs, k_sigma: float = 3.0, band_sigma: float = 5.0):
+    def plan(self, jobs, k_sigma: float = 3.0, band_sigma: float = 5.0, k_sigma_wide: float | None = None,
+             split_z: int | None = None):
         """Copies of the job dicts with the learned n0, backoff step and band
-        (nz_prefill_plan)."""
+        (nz_prefill_plan).  k_sigma_wide: the prefill depth of the jobs wider
+        than split_z (the second group when a batch runs as two groups)."""
         y = self.forward([j["zone_mask"] for j in jobs], [j["L"] for j in jobs])
+        return plan_outputs(y, jobs, k_sigma, band_sigma, k_sigma_wide, split_z)
+
+
+# widest neighbourhood of the first group when the library splits a batch and
+# no split is given (nz_tuning.split_z = 0)
+SPLIT_Z_DEFAULT = 64
+
+
+def plan_outputs(y, jobs, k_sigma: float, band_sigma: float = 5.0, k_sigma_wide: float | None = None,
+                 split_z: int | None = None):
+    """nz_prefill_plan of the MLP outputs y (one row per job), with prefill
+    depth k_sigma_wide for the jobs whose coordination number exceeds split_z
+    when it is given."""
+    if k_sigma_wide is None:
         return nz.nz_prefill_plan(y, jobs, k_sigma, band_sigma)
+    sz = int(split_z) if split_z else SPLIT_Z_DEFAULT
+    yy = np.asarray(y, dtype=np.float32).reshape(-1, OUT)
+    wide = [nz.nz_coordination(int(j["zone_mask"])) > sz for j in jobs]
+    out = [None] * len(jobs)
+    for flag, k in ((False, k_sigma), (True, k_sigma_wide)):
+        idx = [i for i, w in enumerate(wide) if w == flag]
+        if idx:
+            for i, p in zip(idx, nz.nz_prefill_plan(yy[idx], [jobs[i] for i in idx], k, band_sigma)):
+                out[i] = p
+    return out
 
 
 def plan_band_only(model: PrefillModel, jobs, band_sigma: float = 5.0):

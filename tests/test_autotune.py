@@ -2,6 +2,7 @@
 table lookup and the choice for a mixed batch (not GPU)."""
 import json
 
+import numpy as np
 import pytest
 
 from paper_2607_18991_amd import autotune, nz
@@ -101,3 +102,26 @@ def test_batch_plan_and_split_candidates():
     with pytest.raises(nz.NzError):
         nz.nz_batch_workspace_bytes(jobs, dict(split_z=5))
     assert all(k > 0 for k in autotune.K_SIGMA)
+    # a plan with its own depth for the wide jobs: None values are dropped
+    autotune.add_batch(table, jobs, {"tune": {}, "plan": {"k_sigma": 2.5, "k_sigma_wide": 1.5, "split_z": None}}, "b")
+    assert autotune.plan_for(jobs, table) == {"k_sigma": 2.5, "k_sigma_wide": 1.5}
+
+
+def test_plan_outputs_wide_depth():
+    """learned.plan_outputs plans the jobs wider than split_z with their own
+    prefill depth and the rest as nz_prefill_plan does, in the callers' order."""
+    from paper_2607_18991_amd import learned
+
+    jobs = [dict(L=16, zone_mask=m, seed=1, nsamples=10) for m in (0x01, 0x7F, 0x03, 0x3F)]
+    y = np.array([[np.log(0.14), np.log(0.004)], [np.log(0.0019), np.log(0.0002)],
+                  [np.log(0.033), np.log(0.001)], [np.log(0.003), np.log(0.0003)]], dtype=np.float32)
+    same = learned.plan_outputs(y, jobs, 2.5)
+    assert same == nz.nz_prefill_plan(y, jobs, 2.5, 5.0)
+    mixed = learned.plan_outputs(y, jobs, 2.5, k_sigma_wide=1.0, split_z=64)
+    wide = nz.nz_prefill_plan(y, jobs, 1.0, 5.0)
+    for i, j in enumerate(jobs):
+        expect = wide[i] if nz.nz_coordination(j["zone_mask"]) > 64 else same[i]
+        assert mixed[i] == expect
+    assert mixed[1]["n0"] > same[1]["n0"] and mixed[0]["n0"] == same[0]["n0"]
+    # the split defaults to the library's own (zones 1 and 1-2 narrow)
+    assert learned.plan_outputs(y, jobs, 2.5, k_sigma_wide=1.0) == mixed

@@ -77,8 +77,8 @@ def _learned_and_plain(jobs, ws_cap_gb=None, tuned=False):
     from paper_2607_18991_amd import autotune, learned
 
     model = learned.PrefillModel.load()
-    k = autotune.plan_for(model.plan(jobs)).get("k_sigma", 3.0) if tuned else 3.0
-    jl, jp = model.plan(jobs, k_sigma=k), learned.plan_band_only(model, jobs)
+    plan = autotune.plan_for(model.plan(jobs)) if tuned else {}
+    jl, jp = model.plan(jobs, **plan), learned.plan_band_only(model, jobs)
     ln, lm = _run(jl, ws_cap_gb, tune=(autotune.for_jobs(jl) or None) if tuned else None)
     pn, pm = _run(jp, ws_cap_gb, tune=(autotune.for_jobs(jp) or None) if tuned else None)
     bad = np.nonzero((ln != pn) | (lm != pm))[0]
