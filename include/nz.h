@@ -96,8 +96,9 @@ int nz_canonical(const uint64_t *hist, int64_t hist_len, const double *p_grid, i
  * observable of eqs. (5)-(6) (P_max = S_max / L^5 before the convolution).
  * The sweep runs on past n* through the window, one site per step.
  *   boundary   NZ_FREE or NZ_PERIODIC (L >= 5);
- *   n0         -1: plain sweep; else 0 <= n0 < n_lo: the sites of rank < n0
- *              (keys below floor(n0 / N * 2^64)) are labelled in bulk first
+ *   n0         -1: plain sweep; else 0 <= n0 < n_lo: the sites whose keys lie
+ *              below floor(n0 / N * 2^64), rounded down to a multiple of 2^32
+ *              (about the n0 lowest-ranked sites) are labelled in bulk first
  *              (if that count reaches the window, n0 is halved and the sample
  *              redone);
  *   1 <= n_lo < n_hi <= N;
@@ -127,7 +128,8 @@ int nz_convolve_window(const double *Q, int64_t n_lo, int64_t n_hi, int64_t N, c
  *   n0        -1: plain sweep from the empty lattice.
  *             >= 0: learned prefill (Sec. II.B construction started from a
  *             bulk state): every site whose key lies below
- *             floor(n0 / N * 2^64) is occupied at once and its clusters are
+ *             floor(n0 / N * 2^64), rounded down to a multiple of 2^32
+ *             (about n0 sites), is occupied at once and its clusters are
  *             labelled by parallel connected components; the sequential sweep
  *             continues from there.  If that bulk state already spans, the
  *             sample backs off to n0 - backoff, then n0 - 3 backoff,

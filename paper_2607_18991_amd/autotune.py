@@ -137,7 +137,7 @@ def batch_candidates():
 
 
 # widest neighbourhood of the first group when a batch runs as two groups
-SPLIT_Z = (64, 130, 170, 242, 340)
+SPLIT_Z = (10, 64, 130, 170, 242, 340)
 # prefill depth: n0 = (mean - k std) N
 K_SIGMA = (3.0, 2.5, 2.0, 1.5, 1.0)
 

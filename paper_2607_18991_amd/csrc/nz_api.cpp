@@ -252,6 +252,17 @@ uint64_t rank_to_key(int64_t n, int64_t N)
     return static_cast<uint64_t>(v);
 }
 
+// Prefill key threshold for rank n: rank_to_key rounded down to a multiple of
+// 2^32, so that the keys kernel tests keys against it (and against the band's
+// end, a whole number of buckets of at least 2^32 keys above it) by their high
+// words.  The prefill is whatever lies below the threshold: n* and the mass
+// never depend on it, and the rounding moves it by under N / 2^32 sites.
+uint64_t prefill_key(int64_t n, int64_t N)
+{
+    const uint64_t t = rank_to_key(n, N) & ~0xFFFFFFFFull;
+    return t != 0 ? t : rank_to_key(n, N);   // (n >= 1 and N < 2^32 keep it nonzero)
+}
+
 struct Sizes {
     uint64_t T0;
     int32_t nb, cap, shift, full, prefix_cap;
@@ -268,7 +279,7 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
 {
     Sizes s{};
     const int64_t N = pow5(p.L);
-    s.T0 = p.n0 > 0 ? rank_to_key(p.n0, N) : 0;
+    s.T0 = p.n0 > 0 ? prefill_key(p.n0, N) : 0;
     int lgN = 0;
     while ((int64_t(1) << lgN) < N) ++lgN;
     int shift = 64 + bucket_log2 - lgN - p.shift_adj;
@@ -290,7 +301,7 @@ Sizes plan_sizes(const Plan &p, int bucket_log2)
     s.n0b[1] = (s.n0b[0] > 0 && s.n0b[0] - 2 * p.backoff > 0) ? s.n0b[0] - 2 * p.backoff : 0;
     int32_t nb_alloc = s.nb;
     for (int l = 0; l < 2; ++l) {
-        s.T0b[l] = s.n0b[l] > 0 ? rank_to_key(s.n0b[l], N) : 0;
+        s.T0b[l] = s.n0b[l] > 0 ? prefill_key(s.n0b[l], N) : 0;
         s.nbb[l] = s.n0b[l] > 0 ? buckets(s.T0b[l]) : 0;
         nb_alloc = std::max(nb_alloc, s.nbb[l]);
     }

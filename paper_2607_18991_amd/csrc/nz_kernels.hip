@@ -238,7 +238,8 @@ __device__ __forceinline__ void keys_bucket(const KeysCtx &c, uint64_t K, uint32
 // The iterations of one wave over a block: keys, the prefill and band masks,
 // the prefill ballots (lane it keeps iteration it's) and the band queue.
 // FULL: the block lies wholly inside the lattice (no site needs a range test);
-// BALL: the band reaches 2^64 (every key at or above T0 is in it).
+// BALL: the band reaches 2^64 (every key at or above T0 is in it); HI: T0 and
+// the band's end are multiples of 2^32, so comparing high words decides.
 struct KeysIter {
     const KeysCtx &c;
     uint64_t *qk;
@@ -250,7 +251,7 @@ struct KeysIter {
     uint32_t seed_lo, seed_hi, smp_lo, smp_hi;
 };
 
-template <bool FULL, bool BALL>
+template <bool FULL, bool BALL, bool HI>
 __device__ __forceinline__ void keys_iters(const KeysIter &k, uint32_t &be_lo, uint32_t &be_hi, uint32_t &bo_lo,
                                            uint32_t &bo_hi, int &its, uint32_t &nq)
 {
@@ -268,10 +269,21 @@ __device__ __forceinline__ void keys_iters(const KeysIter &k, uint32_t &be_lo, u
         // band_end), combined on the scalar unit
         const uint64_t vm0 = FULL ? ~0ull : __builtin_amdgcn_uicmp(wbase + lane2, k.N, kIcmpUlt);
         const uint64_t vm1 = FULL ? ~0ull : __builtin_amdgcn_uicmp(wbase + lane2 + 1u, k.N, kIcmpUlt);
-        const uint64_t be = vm0 & __builtin_amdgcn_uicmpl(K0, c.T0, kIcmpUlt);
-        const uint64_t bo = vm1 & __builtin_amdgcn_uicmpl(K1, c.T0, kIcmpUlt);
-        const uint64_t qe = (vm0 & ~be) & (BALL ? ~0ull : __builtin_amdgcn_uicmpl(K0, k.band_end, kIcmpUlt));
-        const uint64_t qo = (vm1 & ~bo) & (BALL ? ~0ull : __builtin_amdgcn_uicmpl(K1, k.band_end, kIcmpUlt));
+        uint64_t be, bo, qe, qo;
+        if constexpr (HI) {
+            // T0 and band_end are multiples of 2^32: the keys' high words decide
+            const uint32_t h0 = static_cast<uint32_t>(K0 >> 32), h1 = static_cast<uint32_t>(K1 >> 32);
+            const uint32_t t0 = static_cast<uint32_t>(c.T0 >> 32), te = static_cast<uint32_t>(k.band_end >> 32);
+            be = vm0 & __builtin_amdgcn_uicmp(h0, t0, kIcmpUlt);
+            bo = vm1 & __builtin_amdgcn_uicmp(h1, t0, kIcmpUlt);
+            qe = (vm0 & ~be) & (BALL ? ~0ull : __builtin_amdgcn_uicmp(h0, te, kIcmpUlt));
+            qo = (vm1 & ~bo) & (BALL ? ~0ull : __builtin_amdgcn_uicmp(h1, te, kIcmpUlt));
+        } else {
+            be = vm0 & __builtin_amdgcn_uicmpl(K0, c.T0, kIcmpUlt);
+            bo = vm1 & __builtin_amdgcn_uicmpl(K1, c.T0, kIcmpUlt);
+            qe = (vm0 & ~be) & (BALL ? ~0ull : __builtin_amdgcn_uicmpl(K0, k.band_end, kIcmpUlt));
+            qo = (vm1 & ~bo) & (BALL ? ~0ull : __builtin_amdgcn_uicmpl(K1, k.band_end, kIcmpUlt));
+        }
         if (lane == static_cast<uint32_t>(it)) {
             be_lo = static_cast<uint32_t>(be);
             be_hi = static_cast<uint32_t>(be >> 32);
@@ -374,18 +386,29 @@ __device__ __forceinline__ void keys_block(const NzSample *__restrict__ desc, co
     // whether the band reaches 2^64
     const bool full = __builtin_amdgcn_readfirstlane(wave_base + KEYS_WAVE_SITES <= N ? 1u : 0u) != 0u;
     const bool ball = __builtin_amdgcn_readfirstlane(band_all ? 1u : 0u) != 0u;
+    // thresholds on 2^32 boundaries (the planner's choice): 32-bit compares
+    const bool hi = __builtin_amdgcn_readfirstlane(
+                        ((c.T0 | (band_all ? 0ull : band_end)) & 0xFFFFFFFFull) == 0ull ? 1u : 0u) != 0u;
     // even / odd prefill ballots of iteration it, held by lane it
     uint32_t be_lo = 0, be_hi = 0, bo_lo = 0, bo_hi = 0;
     int its = 0;            // iterations this wave ran (wave-uniform)
     // the loop is compiled for each combination of the two wave-uniform
     // choices, so that no iteration tests them
     KeysIter ki{c, qk, qs, N, wave_base, lane, band_end, seed_lo, seed_hi, smp_lo, smp_hi};
-    if (full) {
-        if (ball) keys_iters<true, true>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
-        else keys_iters<true, false>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+    if (hi) {
+        if (full) {
+            if (ball) keys_iters<true, true, true>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+            else keys_iters<true, false, true>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+        } else {
+            if (ball) keys_iters<false, true, true>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+            else keys_iters<false, false, true>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+        }
+    } else if (full) {
+        if (ball) keys_iters<true, true, false>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+        else keys_iters<true, false, false>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
     } else {
-        if (ball) keys_iters<false, true>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
-        else keys_iters<false, false>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+        if (ball) keys_iters<false, true, false>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
+        else keys_iters<false, false, false>(ki, be_lo, be_hi, bo_lo, bo_hi, its, nq);
     }
     if (lane < nq) keys_bucket(c, qk[lane], qs[lane]);
 
