@@ -195,9 +195,8 @@ def rooflines(summ, res, steps, N, prof):
     nlab = summ["labelling_dispatches_per_step"]
     if summ["prefill_alg_bytes"] > 0 and nlab > 0:
         lab_ms = sum(lab.values())
-        t, _ = traffic_of(prof, ["nz::nz_hook_kernel", "nz::nz_compress_kernel", "nz::nz_accum_kernel",
-                                 "nz::nz_expand_kernel"])
-        r = hbm_roofline("bulk labelling (nz_hook_kernel, nz_compress_kernel, nz_accum_kernel, nz_expand_kernel)",
+        t, _ = traffic_of(prof, ["nz::nz_hook_kernel", "nz::nz_compress_kernel", "nz::nz_accum_kernel"])
+        r = hbm_roofline("bulk labelling (nz_hook_kernel, nz_compress_kernel, nz_accum_kernel)",
                          summ["prefill_alg_bytes"], lab_ms, nlab, t / nlab if t else None)
         r["kernel_ms_split"] = {k: v / nlab for k, v in lab.items()}
         out["roofline_prefill"] = r

@@ -276,8 +276,9 @@ int nz_last_batch_timing(double ms[6]);
 /* With timing on, the bulk labelling of free-boundary prefills split by kernel
  * (HIP events on the launch stream around every dispatch, in-chunk backoff
  * passes included): ms[0..3] = milliseconds summed over dispatches in the hook,
- * compress, size-and-flag and expand kernels, ms[4] = number of dispatches of
- * each. */
+ * compress and size kernels (the size pass also writes the prefilled sites'
+ * lattice entries) and 0 (no separate expand pass), ms[4] = number of
+ * dispatches of each. */
 int nz_last_batch_cc_timing(double ms[5]);
 
 /*

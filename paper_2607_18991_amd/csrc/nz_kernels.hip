@@ -629,7 +629,14 @@ __device__ __forceinline__ bool xcd_slot(int32_t nlist, int32_t bx, int32_t &y, 
 // of a sample is 4 bytes per prefilled site and stays in the L2 of the XCD that
 // holds the sample.  The list position of an occupied neighbour t is the
 // position of its bitset word (wpos) plus the set bits below t in that word.
-// The expand pass writes the lattice parent words the sweep reads.
+// The size pass points the lattice entry of every prefilled site at the list
+// node of its cluster's root; the prefilled roots keep their root words in the
+// list forest, where the sweep reads and updates them.
+
+// A union-find node id: a lattice site s (< 2^29) or LIST_NODE | i, list entry
+// i of the sample's prefilled sites.  Parent entries hold node ids or root
+// words (bit 31 set).
+constexpr int32_t LIST_NODE = 0x20000000;
 
 // Hook: one lane per prefilled site and its forward half of the offset table
 // (one of each +-d pair), eight neighbour words loaded at a time.  The edges a
@@ -822,10 +829,14 @@ __global__ __launch_bounds__(256) void nz_compress_kernel(const NzSample *__rest
     }
 }
 
-// Sizes and border flags of the prefilled clusters: members add themselves to
-// their root word.  No atomic here returns a value, so no wave waits on one; a
-// root that ends up with both border flags (the state already spans, and the
-// sample backs off) is found by the expand pass, which reads every root word.
+// Sizes, border flags and lattice entries of the prefilled sites, in one pass
+// over the list: a member adds itself to its root's word in the list forest,
+// and the lattice entry of every prefilled site points at the list node of its
+// cluster's root (its own node for a root), where the sweep reads and updates
+// the root word.  The flag OR returns the previous word, so the member that
+// completes a root's pair of border flags sees it: the state already spans and
+// the sample backs off (not in largest-cluster runs, which stop below the
+// window instead).
 __global__ __launch_bounds__(256) void nz_accum_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
                                                        int32_t nlist, int32_t bx, uint8_t *__restrict__ ws,
                                                        NzState *__restrict__ state)
@@ -841,42 +852,23 @@ __global__ __launch_bounds__(256) void nz_accum_kernel(const NzSample *__restric
         return;
     }
     const uint32_t L = static_cast<uint32_t>(d.L);
-    int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_parc);
-    const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
-    for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
-        const int32_t r = par[k];
-        if (r >= 0) {
-            uint32_t *root = reinterpret_cast<uint32_t *>(&par[r]);
-            atomicAdd(root, 1u);
-            const uint32_t fl = d.periodic ? 0u : border_flags(prefix[k], L, d.magic);
-            if (fl) (void)atomicOr(root, fl);
-        }
-    }
-}
-
-// Expand: the lattice parent word of every prefilled site, from the list
-// forest (a root keeps its root word, a member points at its root's site).  A
-// root word with both border flags means the prefilled state already spans:
-// the sample backs off (not in largest-cluster runs, which stop below the
-// window instead).
-__global__ __launch_bounds__(256) void nz_expand_kernel(const NzSample *__restrict__ desc, const int32_t *__restrict__ list,
-                                                        int32_t nlist, int32_t bx, uint8_t *__restrict__ ws,
-                                                        NzState *__restrict__ state)
-{
-    int32_t y, x;
-    if (!xcd_slot(nlist, bx, y, x)) return;
-    const int sid = list[y];
-    const NzSample &d = desc[sid];
-    const int32_t n0 = state[sid].n0;
-    if (n0 > d.prefix_cap || d.wrap) return;
+    int32_t *parc = reinterpret_cast<int32_t *>(ws + d.off_parc);
     int32_t *par = reinterpret_cast<int32_t *>(ws + d.off_par);
-    const int32_t *parc = reinterpret_cast<const int32_t *>(ws + d.off_parc);
     const uint32_t *prefix = reinterpret_cast<const uint32_t *>(ws + d.off_prefix);
     bool spans = false;
     for (int32_t k = x * 256 + static_cast<int32_t>(threadIdx.x); k < n0; k += bx * 256) {
-        const int32_t v = parc[k];
-        par[prefix[k]] = v < 0 ? v : static_cast<int32_t>(prefix[v]);
-        spans = spans || (v < 0 && (static_cast<uint32_t>(v) & NZ_FLAGS) == NZ_FLAGS);
+        const int32_t r = parc[k];
+        const uint32_t site = prefix[k];
+        if (r >= 0) {
+            uint32_t *root = reinterpret_cast<uint32_t *>(&parc[r]);
+            atomicAdd(root, 1u);
+            const uint32_t fl = d.periodic ? 0u : border_flags(site, L, d.magic);
+            if (fl) {
+                const uint32_t old = atomicOr(root, fl);
+                spans = spans || ((old | fl) & NZ_FLAGS) == NZ_FLAGS;
+            }
+        }
+        par[site] = LIST_NODE | (r >= 0 ? r : k);
     }
     if (spans && !d.smax_mode) state[sid].status = NZ_ST_BACKOFF;
 }
@@ -938,6 +930,7 @@ template <int RES>
 struct SweepMem {
     uint32_t *occ_g;
     int32_t *par_g;
+    int32_t *parc_g;    // the list forest of the prefilled sites (node ids LIST_NODE | i)
     uint32_t lbase;     // first LDS word of this wave's slice
     uint32_t occ_words; // bitset words (padded to 64 sites)
     uint32_t sshift;    // summary: log2 of bitset words per bit
@@ -992,13 +985,19 @@ struct SweepMem {
         else
             __hip_atomic_fetch_and(&lds[lbase + w], ~bits, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
     }
+    // parent entry of node i (a lattice site, or a list node of the prefill)
     __device__ __forceinline__ int32_t par_ld(uint32_t *lds, int32_t i) const
     {
+        if (i >= LIST_NODE) return ld_w(&parc_g[i - LIST_NODE]);
         if constexpr (RES == RES_ALL) return static_cast<int32_t>(ld_w(&lds[lbase + occ_words + i]));
         else return ld_w(&par_g[i]);
     }
     __device__ __forceinline__ void par_st(uint32_t *lds, int32_t i, int32_t v) const
     {
+        if (i >= LIST_NODE) {
+            st_w(&parc_g[i - LIST_NODE], v);
+            return;
+        }
         if constexpr (RES == RES_ALL) st_w(&lds[lbase + occ_words + i], static_cast<uint32_t>(v));
         else st_w(&par_g[i], v);
     }
@@ -1266,8 +1265,8 @@ __device__ __forceinline__ void sweep_step(const SweepMem<RES> &m, uint32_t *lds
 // one site at a time, which yields the exact n* and mass.
 //
 // While a block is processed its sites are marked occupied and their parent
-// entries hold BLK_MARK | position, a value no parent index reaches (N < 2^29)
-// and no root word has (bit 31 clear).  An occupied neighbour whose parent
+// entries hold BLK_MARK | position, a value no node id reaches (sites below
+// 2^29, list nodes below 2^30) and no root word has (bit 31 clear).  An occupied neighbour whose parent
 // entry carries the mark is a site of the block, earlier or later in the order.
 //
 // Per-wave LDS slice (32-bit words, at the end of the wave's slice):
@@ -1554,6 +1553,7 @@ __global__ __launch_bounds__(256) void nz_sweep_kernel(NzSweepArgs a, SweepOut o
         SweepMem<RES> m;
         m.occ_g = reinterpret_cast<uint32_t *>(a.ws + d.off_occ);
         m.par_g = reinterpret_cast<int32_t *>(a.ws + d.off_par);
+        m.parc_g = reinterpret_cast<int32_t *>(a.ws + d.off_parc);
         m.lbase = wave * a.lds_words;
         m.occ_words = static_cast<uint32_t>(((N + 63) >> 6) << 1);
         m.sshift = static_cast<uint32_t>(d.sum_shift);
@@ -2110,6 +2110,7 @@ __global__ __launch_bounds__(256) void nz_wrap_sweep_kernel(NzSweepArgs a, Sweep
         SweepMem<RES_HBM> m;
         m.occ_g = reinterpret_cast<uint32_t *>(a.ws + d.off_occ);
         m.par_g = nullptr;   // the occupancy side only; entries go through pw
+        m.parc_g = nullptr;
         m.lbase = 0;
         m.occ_words = 0;
         m.sshift = 0;
@@ -2268,9 +2269,7 @@ hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nli
     hipLaunchKernelGGL(nz_accum_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list, nlist,
                        bx_site, ws, state);
     mark(3);
-    hipLaunchKernelGGL(nz_expand_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
-                       nlist, bx_site, ws, state);
-    mark(4);
+    mark(4);   // (the lattice entries are written by the size pass)
     if (smax)
         hipLaunchKernelGGL(nz_rootmax_kernel, dim3(static_cast<uint32_t>(bx_site) * slots8), dim3(256), 0, st, desc, list,
                            nlist, bx_site, ws, state);
