@@ -92,8 +92,8 @@ def run_mode(nz, torch, make_jobs, steps, warmup, tune):
 def prefill_bytes(n0_sites: float, z: int, N: int, samples: int) -> float:
     """Algorithmic HBM bytes of the bulk labelling: per labelled site z/8
     occupancy bits and 16 bytes of hook-and-compress forest traffic, plus 8
-    bytes for the size-and-flag finalisation, and one pass over each prefilled
-    sample's N/8-byte bitset."""
+    bytes for the size pass (the root word's update and the site's lattice
+    entry), and one pass over each prefilled sample's N/8-byte bitset."""
     return n0_sites * (z / 8.0 + 24.0) + samples * N / 8.0
 
 
