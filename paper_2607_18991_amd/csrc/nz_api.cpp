@@ -259,6 +259,8 @@ uint64_t rank_to_key(int64_t n, int64_t N)
 // never depend on it, and the rounding moves it by under N / 2^32 sites.
 uint64_t prefill_key(int64_t n, int64_t N)
 {
+    // test hook: the unrounded threshold drives the keys kernel's 64-bit compares
+    if (getenv("NZ_DEBUG_EXACT_T0")) return rank_to_key(n, N);
     const uint64_t t = rank_to_key(n, N) & ~0xFFFFFFFFull;
     return t != 0 ? t : rank_to_key(n, N);   // (n >= 1 and N < 2^32 keep it nonzero)
 }

@@ -46,6 +46,35 @@ def test_prefill_exact(L):
     assert stats["backoffs"] == int(back.sum())
 
 
+@pytest.mark.parametrize("tune", [dict(residency=1), dict(residency=3), dict(sweep_mode=1),
+                                  dict(sweep_mode=2, residency=3), dict(sweep_mode=1, residency=3)])
+def test_prefill_every_residency(tune):
+    """Prefilled sites enter the sweep as list nodes of the bulk labelling's
+    forest: with the bitset, or bitset and parents, in LDS and with either
+    step shape, results equal the oracle's."""
+    L = 6
+    jobs = []
+    for m in (0x01, 0x07, 0x7F):
+        med, sd = typical_nstar(L, m)
+        jobs.append(dict(L=L, zone_mask=m, seed=5150, nsamples=24, n0=max(1, med - 2 * sd), backoff=2 * sd))
+    gn, gm, _, _ = run_batch(jobs, tune=tune)
+    assert_same(jobs, gn, gm, *oracle_batch(jobs))
+
+
+def test_prefill_exact_thresholds():
+    """With the prefill thresholds left unrounded (test hook), the keys kernel
+    classifies sites by full 64-bit compares; results equal the oracle's."""
+    L = 8
+    jobs = []
+    for m in (0x01, 0x0F, 0x7F):
+        med, sd = typical_nstar(L, m)
+        jobs.append(dict(L=L, zone_mask=m, seed=6161, nsamples=24, n0=max(1, med - 2 * sd), backoff=2 * sd))
+    with env(NZ_DEBUG_EXACT_T0=1):
+        gn, gm, back, stats = run_batch(jobs)
+    assert_same(jobs, gn, gm, *oracle_batch(jobs))
+    assert stats["prefilled_sites"] > 0
+
+
 def test_forced_backoff():
     L = 6
     N = L**5
