@@ -32,8 +32,9 @@ thread_local double g_ms[6] = {0, 0, 0, 0, 0, 0};
 // per job of the last batch (caller's job order): sequential additions and
 // sites occupied by the bulk prefill, summed over the final runs of its samples
 thread_local std::vector<int64_t> g_job_serial, g_job_pre;
-// bulk-labelling kernels of the last batch: milliseconds in hook, compress,
-// size pass, expand (summed over dispatches) and the number of dispatches
+// bulk-labelling kernels of the last batch: milliseconds in hook, compress and
+// the size pass (summed over dispatches), 0 (no separate expand pass) and the
+// number of dispatches
 thread_local double g_cc_ms[5] = {0, 0, 0, 0, 0};
 
 // Events around each kernel of the bulk labelling; a chunk launches it up to

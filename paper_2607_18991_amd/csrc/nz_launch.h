@@ -29,7 +29,8 @@ hipError_t launch_sort(const NzSample *desc, int32_t nsamp, int32_t max_nb, int3
 // wrap: the listed samples are periodic first-wrap samples (64-bit entries).
 // periodic: the listed samples have periodic coordinates (all or none of them).
 // ev (may be NULL): five events recorded before the hook, after it, after
-// compress, after the size pass and after expand (free-boundary samples).
+// compress and after the size pass, the fifth with the fourth (the size pass
+// writes the lattice entries; there is no separate expand pass).
 hipError_t launch_prefill(const NzSample *desc, const int32_t *list, int32_t nlist, int32_t bx_hook, int32_t bx_site,
                           const NzOffset *tabs, uint8_t *ws, NzState *state, bool smax, bool wrap, bool periodic,
                           hipStream_t st, hipEvent_t *ev = nullptr);
