@@ -10,12 +10,17 @@ from paper_2607_18991_amd import nz
 THREADS = max(1, min(16, os.cpu_count() or 1))
 
 
-def run_batch(jobs, tune=None, ws_bytes=None):
+def run_batch(jobs, tune=None, ws_bytes=None, fill=None):
+    """fill: a byte value the workspace is set to before the batch (None:
+    left as allocated)."""
     import torch
 
     total = sum(int(j["nsamples"]) for j in jobs)
     need = nz.nz_batch_workspace_bytes(jobs, tune)
-    ws = torch.empty(ws_bytes or need, dtype=torch.uint8, device="cuda")
+    if fill is None:
+        ws = torch.empty(ws_bytes or need, dtype=torch.uint8, device="cuda")
+    else:
+        ws = torch.full((ws_bytes or need,), fill, dtype=torch.uint8, device="cuda")
     dn = torch.full((max(total, 1),), -7, dtype=torch.int32, device="cuda")
     dm = torch.full((max(total, 1),), -7, dtype=torch.int32, device="cuda")
     back = nz.nz_sweep_batch(jobs, ws, dn, dm, tune=tune)

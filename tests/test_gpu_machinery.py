@@ -146,6 +146,32 @@ def test_block_fallback_path(cap, residency):
     assert_same(jobs, gn, gm, *oracle_batch(jobs))
 
 
+@pytest.mark.parametrize("tune", [dict(), dict(sweep_mode=1), dict(residency=1), dict(sweep_mode=2, residency=1)])
+def test_workspace_bytes_written_before_read(tune):
+    """Every workspace byte a kernel reads was written earlier in the same
+    batch: with the workspace set to 0xFF bytes first (a parent entry of -1
+    would read as a spanning root, a list position of 2^32 - 1 would leave the
+    forest), results still equal the oracle's.  L = 9 gives each sample eight
+    ranges of the keys kernel, so the sparse prefills of the wide
+    neighbourhoods leave whole ranges without a prefilled site; plain,
+    prefilled and periodic first-wrap samples run together."""
+    import oracle
+    from paper_2607_18991_amd import nz
+
+    L = 9
+    jobs = []
+    for m in (0x01, 0x07, 0x7F, 0x48):
+        med, sd = typical_nstar(L, m)
+        jobs.append(dict(L=L, zone_mask=m, seed=777, nsamples=16, n0=max(1, med - 2 * sd), backoff=2 * sd))
+    jobs.append(dict(L=L, zone_mask=0x03, seed=778, nsamples=16))
+    ns, _ = oracle.sweep_many(L, 0x03, 999, 0, 16, nthreads=8, periodic=True)
+    med, sd = int(np.median(ns)), int(max(1, ns.std()))
+    jobs.append(dict(L=L, zone_mask=0x03, seed=779, nsamples=16, n0=max(1, med - 2 * sd), backoff=2 * sd,
+                     boundary=nz.NZ_PERIODIC))
+    gn, gm, _, _ = run_batch(jobs, tune=tune, fill=0xFF)
+    assert_same(jobs, gn, gm, *oracle_batch(jobs))
+
+
 @pytest.mark.parametrize("L", [9, 12])
 def test_block_matches_single_site(L):
     """The 64-site block sweep and the one-site sweep agree sample by sample on
